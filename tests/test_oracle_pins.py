@@ -1,0 +1,335 @@
+"""Pins of the oracle against facts it does not compute itself.
+
+- the worked example of the Derived Datatypes section (values derived by
+  hand, stored under tests/golden/ with their citation);
+- the YZ-surface segment count of the same section;
+- closed forms of the small-vector, halo-face and particle-record layouts;
+- library routines that reduce to special cases: numpy slicing (subarray,
+  C and Fortran order), numpy strided views (vector), numpy structured
+  dtypes with C alignment (struct padding and field extraction), memcpy
+  (contiguous);
+- brute-force typemap enumeration on random tiny types (every constructor);
+- invariants (chunked partial packs concatenate, unpack inverts pack,
+  count-fold streams concatenate, dup and equivalent constructions agree).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import bruteforce as bf
+import oracle
+from oracle import OracleError, build_type
+from paper_2402_12274_amd import inputs
+from typegen import buffer_for, tiny_specs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------------------
+# worked example
+
+
+def test_worked_example_typeiov():
+    g = _load("typeiov_example.json")
+    t = build_type(g["spec"])
+    a = t.attrs()
+    assert a["size"] == g["size"]
+    assert a["lb"] == g["lb"] and a["extent"] == g["extent"]
+    assert a["true_lb"] == g["true_lb"] and a["true_extent"] == g["true_extent"]
+    assert t.iov_len(g["max_iov_bytes"]) == (g["iov_len"], g["actual_iov_bytes"])
+    base, ln = t.iov(g["iov_offset"], g["max_iov_len"])
+    assert base.tolist() == g["iov_base"]
+    assert ln.tolist() == g["iov_len_each"]
+    assert hex(base[0]) == "0x11e6380c0"
+
+
+def test_yz_surface_segment_count():
+    for case in _load("yz_surface.json")["cases"]:
+        nz, ny, nx = case["dims"]
+        spec = ("subarray", [nz, ny, nx], [nz, ny, 1], [0, 0, case["x"]], "C", ("basic", case["elem"]))
+        t = build_type(spec)
+        base, ln = t.iov(0, case["segments"] + 5)
+        assert t.num_segments() == case["segments"] == len(base)
+        assert set(ln.tolist()) == {case["seg_bytes"]}
+
+
+# ---------------------------------------------------------------------------
+# closed forms of the workload layouts
+
+
+def test_small_vector_closed_form():
+    t = build_type(inputs.vector_small())
+    a = t.attrs()
+    assert a["size"] == 8192
+    assert a["extent"] == a["true_extent"] == 16376
+    assert t.num_segments() == 1024
+    base, ln = t.iov(0, 1024)
+    assert (base == 16 * np.arange(1024)).all() and (ln == 8).all()
+    assert t.iov_len(-1) == (1024, 8192)
+    assert t.iov_len(4096) == (512, 4096)
+    assert t.iov_len(4100) == (512, 4096)
+    assert t.iov(512, 3)[0][0] == 8192
+
+
+@pytest.mark.parametrize("w", [1, 4])
+def test_halo_face_closed_forms(w):
+    n = 64
+    m = n - 2 * w
+    for label, spec in inputs.halo_faces(n, (w,)):
+        t = build_type(spec)
+        dim = int(label.split("-")[1][1])
+        a = t.attrs()
+        assert a["size"] == m * m * w * 8
+        assert a["lb"] == 0 and a["extent"] == n ** 3 * 8
+        nseg = t.num_segments()
+        base, ln = t.iov(0, nseg)
+        if dim == 2:   # fastest dim fixed: one w-wide block per (z, y)
+            assert nseg == m * m and set(ln.tolist()) == {8 * w}
+        elif dim == 1:  # one interior row per (z, y in face)
+            assert nseg == m * w and set(ln.tolist()) == {8 * m}
+        else:           # slowest fixed: interior rows of each plane
+            assert nseg == w * m and set(ln.tolist()) == {8 * m}
+
+
+def test_halo_face_full_size_w1():
+    # 512^3 array: most-fragmented face has 510^2 segments of 8 B
+    t = build_type(inputs.halo_face(512, 1, 2, "lo"))
+    assert t.num_segments() == 260100
+    assert t.attrs()["size"] == 2080800
+    t4 = build_type(inputs.halo_face(512, 4, 2, "hi"))
+    assert t4.num_segments() == 254016
+    assert t4.attrs()["size"] == 8128512
+
+
+def test_particle_struct_matches_numpy_aligned_dtype():
+    t = build_type(inputs.particle_struct())
+    a = t.attrs()
+    dt = np.dtype({"names": ["i", "d", "c"], "formats": ["<i4", ("<f8", 3), "S5"]}, align=True)
+    assert dt.itemsize == 40 and dt.fields["d"][1] == 8 and dt.fields["c"][1] == 32
+    assert a["size"] == 33 and a["extent"] == dt.itemsize and a["true_extent"] == 37
+    base, ln = t.iov(0, 10)
+    assert list(zip(base.tolist(), ln.tolist())) == [(0, 4), (8, 29)]
+    count = 1000
+    buf = inputs.random_bytes(count * 40, seed=5)
+    rec = buf.reshape(count, 40)
+    expect = np.concatenate([rec[:, 0:4], rec[:, 8:37]], axis=1).ravel()
+    got = t.pack(buf, 0, count)
+    assert np.array_equal(got, expect)
+    # 1 MiB-style partial packs: chunks concatenate to the full pack
+    parts = [t.pack(buf, 0, count, off, 997) for off in range(0, count * 33, 997)]
+    assert np.array_equal(np.concatenate(parts), expect)
+
+
+# ---------------------------------------------------------------------------
+# library routines for special cases
+
+
+@pytest.mark.parametrize("order", ["C", "F"])
+def test_subarray_matches_numpy_slicing(order):
+    g = np.random.Generator(np.random.PCG64(11))
+    for _ in range(25):
+        nd = int(g.integers(1, 5))
+        sizes = [int(g.integers(1, 9)) for _ in range(nd)]
+        subs = [int(g.integers(1, s + 1)) for s in sizes]
+        starts = [int(g.integers(0, s - u + 1)) for s, u in zip(sizes, subs)]
+        elem = ["DOUBLE", "INT32", "INT16", "BYTE"][int(g.integers(0, 4))]
+        es = bf.SIZES[elem]
+        t = build_type(("subarray", sizes, subs, starts, order, ("basic", elem)))
+        total = int(np.prod(sizes))
+        buf = inputs.random_bytes(total * es, seed=int(g.integers(0, 1 << 30)))
+        elems = buf.reshape(total, es)
+        # numpy's own row-/column-major indexing of the full array
+        lin = np.arange(total).reshape(sizes, order=order)
+        sl = tuple(slice(s, s + u) for s, u in zip(starts, subs))
+        picked = lin[sl].ravel(order=order)
+        expect = elems[picked].ravel()
+        assert np.array_equal(t.pack(buf, 0, 1), expect)
+        a = t.attrs()
+        assert a["lb"] == 0 and a["extent"] == total * es
+
+
+def test_vector_matches_numpy_strided_view():
+    g = np.random.Generator(np.random.PCG64(12))
+    for _ in range(30):
+        n, bl, st = int(g.integers(1, 40)), int(g.integers(1, 5)), int(g.integers(1, 9))
+        st = max(st, bl)
+        t = build_type(("vector", n, bl, st, inputs.DOUBLE))
+        buf = inputs.random_bytes(((n - 1) * st + bl) * 8, seed=int(g.integers(0, 1 << 30)))
+        f = buf.view(np.float64)
+        view = np.lib.stride_tricks.as_strided(f, shape=(n, bl), strides=(st * 8, 8))
+        assert np.array_equal(t.pack(buf, 0, 1), np.ascontiguousarray(view).view(np.uint8).ravel())
+        assert t.attrs()["extent"] == ((n - 1) * st + bl) * 8
+
+
+def test_contiguous_packs_like_memcpy():
+    buf = inputs.random_bytes(1 << 16, seed=3)
+    t = build_type(("contiguous", 1 << 13, inputs.DOUBLE))
+    assert np.array_equal(t.pack(buf, 0, 1), buf)
+    assert t.num_segments() == 1
+    assert np.array_equal(t.pack(buf, 0, 1, 1000, 12345), buf[1000:13345])
+    t2 = build_type(("contiguous", 100, inputs.BYTE))
+    assert np.array_equal(t2.pack(buf, 0, 300), buf[:30000])
+
+
+# ---------------------------------------------------------------------------
+# brute force on random tiny types
+
+
+SPECS = tiny_specs(20240219, 160)
+
+
+def _attrs_bf(tm):
+    return dict(size=tm.size, lb=tm.lb, ub=tm.ub, true_lb=tm.true_lb, true_ub=tm.true_ub)
+
+
+@pytest.mark.parametrize("i", range(len(SPECS)))
+def test_oracle_vs_bruteforce(i):
+    spec = SPECS[i]
+    tm = bf.typemap(spec)
+    t = build_type(spec)
+    a = t.attrs()
+    assert {k: a[k] for k in ("size", "lb", "ub", "true_lb", "true_ub")} == _attrs_bf(tm), spec
+    assert a["entries"] == len(tm.entries)
+    segs = bf.segments(tm)
+    assert t.num_segments() == len(segs)
+    b, ln = t.iov(0, len(segs) + 3)
+    assert list(zip(b.tolist(), ln.tolist())) == segs
+    for off in range(0, len(segs) + 2):
+        for m in (0, 1, 2, 5):
+            b, ln = t.iov(off, m)
+            assert list(zip(b.tolist(), ln.tolist())) == bf.iov(tm, off, m)
+    for mb in [-1] + list(range(0, tm.size + 2)):
+        assert t.iov_len(mb) == bf.iov_len(tm, mb), (spec, mb)
+    for count in (0, 1, 3):
+        size, origin = buffer_for(tm, count)
+        buf = inputs.random_bytes(size, seed=i * 7 + count)
+        total = count * tm.size
+        full = bf.pack(tm, buf, origin, count)
+        assert np.array_equal(t.pack(buf, origin, count), full)
+        for off in sorted({0, 1, total // 3, total // 2, max(total - 1, 0), total, total + 5}):
+            for mb in (-1, 0, 1, 7, total):
+                assert np.array_equal(t.pack(buf, origin, count, off, mb),
+                                      bf.pack(tm, buf, origin, count, off, mb)), (spec, count, off, mb)
+        if bf.overlaps(tm, count):
+            with pytest.raises(OracleError) as e:
+                t.unpack(full, np.zeros_like(buf), origin, count)
+            assert e.value.code == oracle.oracle.ERR_OVERLAP
+        else:
+            dst = np.full_like(buf, 0xA5)
+            exp = dst.copy()
+            bf.unpack(tm, full, exp, origin, count)
+            assert t.unpack(full, dst, origin, count) == total
+            assert np.array_equal(dst, exp)
+            if total > 2:
+                # partial unpack at an offset leaves everything else alone
+                dst2 = np.full_like(buf, 0x3C)
+                exp2 = dst2.copy()
+                lo, hi = total // 3, total - 1
+                bf.unpack(tm, full[lo:hi], exp2, origin, count, lo)
+                t.unpack(full[lo:hi], dst2, origin, count, lo)
+                assert np.array_equal(dst2, exp2)
+
+
+# ---------------------------------------------------------------------------
+# invariants and error rules
+
+
+def test_invariants_on_random_types():
+    specs = [s for s in tiny_specs(777, 120, allow_overlap=False) if not bf.overlaps(bf.typemap(s), 3)]
+    assert len(specs) > 40
+    for i, spec in enumerate(specs):
+        t = build_type(spec)
+        a = t.attrs()
+        nseg = t.num_segments()
+        _, ln = t.iov(0, nseg)
+        assert int(ln.sum()) == a["size"]                       # sum of iov lengths = size
+        prev = (0, 0)
+        for mb in range(0, a["size"] + 1):
+            k, act = t.iov_len(mb)
+            assert k >= prev[0] and act >= prev[1]              # monotone
+            assert act <= mb
+            if k < nseg:
+                assert mb < act + ln[k]                         # bisection: P_k <= mb < P_{k+1}
+            prev = (k, act)
+        tm = bf.typemap(spec)
+        count = 3
+        size, origin = buffer_for(tm, count)
+        buf = inputs.random_bytes(size, seed=100 + i)
+        full = t.pack(buf, origin, count)
+        # pack(count) = concatenation of pack(1) at r * extent
+        parts = [t.pack(buf, origin + r * a["extent"], 1) for r in range(count)]
+        assert np.array_equal(full, np.concatenate(parts) if parts else full)
+        # chunked partial packs (1 B, primes) concatenate to the full pack
+        for step in (1, 3, 7, 13):
+            ch = [t.pack(buf, origin, count, o, step) for o in range(0, len(full), step)]
+            assert np.array_equal(np.concatenate(ch) if ch else full, full)
+        # unpack(pack(x)) restores covered bytes and leaves the rest untouched
+        dst = np.zeros_like(buf)
+        t.unpack(full, dst, origin, count)
+        covered = np.zeros(len(buf), bool)
+        covered[origin + bf.stream_addrs(tm, count)] = True
+        assert np.array_equal(dst[covered], buf[covered]) and not dst[~covered].any()
+        # dup is the same type
+        d = build_type(("dup", spec))
+        assert np.array_equal(d.pack(buf, origin, count), full)
+
+
+def test_subarray_equals_nested_hvectors():
+    sizes, subs, starts = [7, 6, 9], [3, 4, 5], [2, 1, 3]
+    E = 8
+    sub = build_type(("subarray", sizes, subs, starts, "C", inputs.DOUBLE))
+    row = ("contiguous", subs[2], inputs.DOUBLE)
+    plane = ("hvector", subs[1], 1, sizes[2] * E, row)
+    box = ("hvector", subs[0], 1, sizes[1] * sizes[2] * E, plane)
+    disp = ((starts[0] * sizes[1] + starts[1]) * sizes[2] + starts[2]) * E
+    nested = build_type(("hindexed", [1], [disp], box))
+    buf = inputs.random_bytes(int(np.prod(sizes)) * E, seed=9)
+    assert np.array_equal(sub.pack(buf, 0, 1), nested.pack(buf, 0, 1))
+    assert sub.num_segments() == nested.num_segments() == subs[0] * subs[1]
+
+
+def test_error_rules():
+    D = inputs.DOUBLE
+    t = build_type(("vector", 4, 1, 2, D))
+    with pytest.raises(OracleError):
+        t.iov_len(-2)                        # only -1 is special
+    with pytest.raises(OracleError):
+        t.iov(-1, 3)
+    assert t.iov(4, 3)[0].size == 0          # offset past the end: nothing
+    assert t.iov_len(2 ** 31 - 1) == (4, 32)  # INT_MAX: all segments
+    buf = inputs.random_bytes(64, seed=1)
+    assert t.pack(buf, 0, 1, 40, -1).size == 0   # offset beyond the stream
+    with pytest.raises(OracleError):
+        t.unpack(np.zeros(40, np.uint8), np.zeros(64, np.uint8), 0, 1)  # truncate
+    with pytest.raises(OracleError) as e:
+        t.unpack(np.zeros(9, np.uint8), np.zeros(64, np.uint8), 0, 1, 24)
+    assert e.value.code == oracle.oracle.ERR_TRUNCATE
+    for bad in [("subarray", [4], [5], [0], "C", D), ("subarray", [4], [2], [3], "C", D),
+                ("subarray", [4], [-1], [0], "C", D), ("vector", -1, 1, 1, D), ("vector", 2, -1, 1, D),
+                ("hindexed", [1, -1], [0, 8], D), ("vector", 2, 1, 2 ** 62, ("vector", 2, 1, 2 ** 62, D))]:
+        with pytest.raises(OracleError):
+            build_type(bad)
+    # overlapping types pack but do not unpack
+    ov = build_type(("hindexed", [2, 2], [0, 8], D))
+    buf = inputs.random_bytes(32, seed=2)
+    p = ov.pack(buf, 0, 1)
+    assert np.array_equal(p, np.concatenate([buf[0:16], buf[8:24]]))
+    with pytest.raises(OracleError) as e:
+        ov.unpack(p, np.zeros(32, np.uint8), 0, 1)
+    assert e.value.code == oracle.oracle.ERR_OVERLAP
+
+
+def test_multithreaded_pack_equals_single():
+    t = build_type(inputs.particle_struct())
+    count = 70000
+    buf = inputs.random_bytes(count * 40, seed=21)
+    one = t.pack(buf, 0, count)
+    assert np.array_equal(t.pack(buf, 0, count, nthreads=4), one)
+    assert np.array_equal(t.pack(buf, 0, count, 123457, 1 << 20, nthreads=3), one[123457:123457 + (1 << 20)])
