@@ -1,0 +1,338 @@
+/*
+ * mdt.h -- C ABI of libmdt: MPI-style derived datatypes on MI355X (gfx950).
+ *
+ * What it implements (arXiv 2402.12274, "Designing and Prototyping
+ * Extensions to MPI in MPICH"):
+ *   - Derived Datatypes section: datatypes as a nested, offset, possibly
+ *     overlapping memory-layout description, and the extension that lets a
+ *     user read a committed datatype's segments as an iovec list
+ *     (MPIX_Type_iov_len, MPIX_Type_iov, MPIX_Iov).  mdt_type_iov_len and
+ *     mdt_type_iov are those two calls; mdt_iov is MPIX_Iov.
+ *   - The gather/scatter that such a layout drives: pack and unpack of
+ *     device-resident buffers, by byte range of the packed stream (General
+ *     Progress, Background: large messages move as pipelined chunks).
+ *   - Offloading Asynchronous Operations section: work enqueued on a GPU
+ *     stream runs in that stream's order; starting it and waiting for it
+ *     are separate host-side steps (mdt_*_enqueue, mdt_wait, mdt_test).
+ *   - MPIX Streams / General Progress sections: a stream is a serial
+ *     execution context; progress can be driven explicitly or by a progress
+ *     thread (mdt_server_progress, mdt_server_start_progress_thread).
+ *
+ * Conventions (apply to every call):
+ *   - Every call returns MDT_SUCCESS (0) or an MDT_ERR_* code.  On error no
+ *     output argument is written and no device work is enqueued.
+ *   - Counts, sizes, displacements and offsets are int64 (mdt_count,
+ *     mdt_aint).  Displacements may be negative.
+ *   - Buffer arguments of pack/unpack are *device* pointers (memory from
+ *     hipMalloc or a framework allocator on the current HIP device) unless
+ *     stated otherwise.  They are owned by the caller and must stay valid
+ *     until the work that uses them has completed.
+ *   - A buffer "origin" is the address of displacement 0 of element 0; the
+ *     typemap's bytes of element r sit at origin + r*extent + displacement.
+ *   - Offsets and budgets of pack/unpack are byte positions in the packed
+ *     stream of (count x type).  Partial ranges may split basic elements.
+ *   - Type handles are reference counted: constructors deep-copy their
+ *     array arguments and hold references to their children, so freeing a
+ *     type never invalidates a type built from it.
+ *   - Threads: type construction, commit and queries are thread safe.  An
+ *     mdt_stream is a serial context: concurrent calls on one stream are a
+ *     caller error; different streams never contend.
+ */
+#ifndef MDT_H
+#define MDT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define MDT_API __attribute__((visibility("default")))
+#else
+#define MDT_API
+#endif
+
+typedef int64_t mdt_count; /* MPI_Count */
+typedef int64_t mdt_aint;  /* MPI_Aint */
+
+typedef struct mdt_type_s *mdt_type;
+typedef struct mdt_stream_s *mdt_stream;
+typedef struct mdt_request_s *mdt_request;
+typedef struct mdt_batch_s *mdt_batch;
+typedef struct mdt_server_s *mdt_server;
+/* Same layout as hipStream_t; kept opaque so this header needs no HIP headers. */
+typedef struct ihipStream_t *mdt_hip_stream;
+
+#define MDT_TYPE_NULL ((mdt_type)0)
+#define MDT_REQUEST_NULL ((mdt_request)0)
+
+/* MPIX_Iov: {base, len}; same layout as struct iovec (Derived Datatypes,
+ * Extension).  Host queries store the segment's byte displacement from the
+ * buffer origin in iov_base (it may be "negative"); the device flatten call
+ * adds a caller-given base address. */
+typedef struct mdt_iov {
+    void *iov_base;
+    mdt_aint iov_len;
+} mdt_iov;
+
+enum {
+    MDT_SUCCESS = 0,
+    MDT_ERR_ARG = 1,      /* invalid argument: negative count, bad bounds, overflow, NULL output */
+    MDT_ERR_TYPE = 2,     /* NULL, freed or (where required) uncommitted type handle */
+    MDT_ERR_COUNT = 3,    /* count out of range for the type (stream length overflows) */
+    MDT_ERR_TRUNCATE = 4, /* unpack input longer than the remaining packed stream */
+    MDT_ERR_OVERLAP = 5,  /* unpack target layout has overlapping bytes */
+    MDT_ERR_NO_MEM = 6,   /* host or device allocation failed, or a size limit was hit */
+    MDT_ERR_HIP = 7,      /* a HIP runtime call failed; see mdt_last_hip_error */
+    MDT_ERR_AGAIN = 8,    /* non-blocking submit: admission budget currently full */
+    MDT_ERR_STATE = 9     /* call not valid in the object's current state */
+};
+
+/* Predefined (basic) types.  A basic type has one entry at displacement 0;
+ * its size, extent and alignment are all equal to its byte size. */
+enum {
+    MDT_CODE_BYTE = 0, MDT_CODE_CHAR, MDT_CODE_INT8, MDT_CODE_UINT8,
+    MDT_CODE_INT16, MDT_CODE_UINT16, MDT_CODE_INT32, MDT_CODE_UINT32,
+    MDT_CODE_INT, MDT_CODE_FLOAT, MDT_CODE_INT64, MDT_CODE_UINT64,
+    MDT_CODE_DOUBLE, MDT_NUM_BASIC
+};
+/* Returns the (never freed, already committed) handle of a predefined type,
+ * or MDT_TYPE_NULL for an unknown code. */
+MDT_API mdt_type mdt_basic(int code);
+#define MDT_BYTE mdt_basic(MDT_CODE_BYTE)
+#define MDT_CHAR mdt_basic(MDT_CODE_CHAR)
+#define MDT_INT8 mdt_basic(MDT_CODE_INT8)
+#define MDT_UINT8 mdt_basic(MDT_CODE_UINT8)
+#define MDT_INT16 mdt_basic(MDT_CODE_INT16)
+#define MDT_UINT16 mdt_basic(MDT_CODE_UINT16)
+#define MDT_INT32 mdt_basic(MDT_CODE_INT32)
+#define MDT_UINT32 mdt_basic(MDT_CODE_UINT32)
+#define MDT_INT mdt_basic(MDT_CODE_INT)
+#define MDT_FLOAT mdt_basic(MDT_CODE_FLOAT)
+#define MDT_INT64 mdt_basic(MDT_CODE_INT64)
+#define MDT_UINT64 mdt_basic(MDT_CODE_UINT64)
+#define MDT_DOUBLE mdt_basic(MDT_CODE_DOUBLE)
+
+enum { MDT_ORDER_C = 0, MDT_ORDER_FORTRAN = 1 };
+
+/* ---------------------------------------------------------------------
+ * Type constructors (Derived Datatypes: nested layouts with offsets; the
+ * worked example builds a contiguous type and a subarray of it).  Each
+ * follows the MPI constructor of the same name; E below is the extent of
+ * the child type.  *out receives a new, uncommitted handle.
+ *   contiguous(n, c):            copy i at i*E, i < n
+ *   vector(n, bl, stride, c):    copy (i, j) at (i*stride + j)*E
+ *   hvector(n, bl, stride, c):   copy (i, j) at i*stride + j*E  (stride in bytes)
+ *   indexed(n, bl[], disp[], c): copy (i, j) at (disp[i] + j)*E, j < bl[i]
+ *   hindexed(...):               copy (i, j) at disp[i] + j*E   (disp in bytes)
+ *   *_block: the same with one block length for all blocks
+ *   struct(n, bl[], disp[], c[]): copy (i, j) of c[i] at disp[i] + j*extent(c[i]);
+ *       the extent is padded up to a multiple of the largest member
+ *       alignment unless a member has explicit bounds (resized/subarray)
+ *   subarray(nd, sizes, subsizes, starts, order, c): the sub-box of an
+ *       nd-dimensional array of c, row-major (C) or column-major (Fortran);
+ *       lb = 0, extent = prod(sizes)*E.  subsizes may be 0 (empty type).
+ *   resized(c, lb, extent): the typemap of c with the given bounds
+ *   dup(c): the same typemap and bounds
+ * Errors: MDT_ERR_ARG for negative counts/lengths, invalid subarray bounds,
+ * NULL arrays with n > 0, or 64-bit overflow of any displacement or bound;
+ * MDT_ERR_TYPE for an invalid child handle. */
+MDT_API int mdt_type_contiguous(mdt_count n, mdt_type old, mdt_type *out);
+MDT_API int mdt_type_vector(mdt_count n, mdt_count bl, mdt_count stride, mdt_type old, mdt_type *out);
+MDT_API int mdt_type_create_hvector(mdt_count n, mdt_count bl, mdt_aint stride_bytes, mdt_type old,
+                                    mdt_type *out);
+MDT_API int mdt_type_indexed(mdt_count n, const mdt_count bl[], const mdt_count disp[], mdt_type old,
+                             mdt_type *out);
+MDT_API int mdt_type_create_hindexed(mdt_count n, const mdt_count bl[], const mdt_aint disp[], mdt_type old,
+                                     mdt_type *out);
+MDT_API int mdt_type_create_indexed_block(mdt_count n, mdt_count bl, const mdt_count disp[], mdt_type old,
+                                          mdt_type *out);
+MDT_API int mdt_type_create_hindexed_block(mdt_count n, mdt_count bl, const mdt_aint disp[], mdt_type old,
+                                           mdt_type *out);
+MDT_API int mdt_type_create_struct(mdt_count n, const mdt_count bl[], const mdt_aint disp[],
+                                   const mdt_type types[], mdt_type *out);
+MDT_API int mdt_type_create_subarray(int ndims, const mdt_count sizes[], const mdt_count subsizes[],
+                                     const mdt_count starts[], int order, mdt_type old, mdt_type *out);
+MDT_API int mdt_type_create_resized(mdt_type old, mdt_aint lb, mdt_aint extent, mdt_type *out);
+MDT_API int mdt_type_dup(mdt_type old, mdt_type *out);
+
+/* Commit (worked example: committed before it is queried): compiles the
+ * layout program and uploads its tables to the current HIP device, where
+ * they stay resident until the last reference is freed.  Committing twice
+ * is a no-op.  Without a GPU the host layout is still built (queries work);
+ * device tables are then uploaded on first device use. */
+MDT_API int mdt_type_commit(mdt_type *t);
+/* Release the caller's reference and set *t = MDT_TYPE_NULL.  Predefined
+ * handles are not freed (MDT_ERR_TYPE).  The device tables of the type are
+ * released when no type refers to it any more; their release waits for the
+ * device to be idle. */
+MDT_API int mdt_type_free(mdt_type *t);
+
+/* Attributes (valid on uncommitted types). */
+MDT_API int mdt_type_size(mdt_type t, mdt_count *size);
+MDT_API int mdt_type_get_extent(mdt_type t, mdt_aint *lb, mdt_aint *extent);
+MDT_API int mdt_type_get_true_extent(mdt_type t, mdt_aint *true_lb, mdt_aint *true_extent);
+
+/* MPIX_Type_iov_len (Derived Datatypes, Extension).  Segments are maximal
+ * runs of the type's bytes that are contiguous in memory and consecutive in
+ * map order.  If max_iov_bytes is -1 or greater than the type size,
+ * *iov_len = number of segments and *actual_iov_bytes = size; otherwise
+ * *iov_len = number of whole leading segments whose bytes fit in
+ * max_iov_bytes, and *actual_iov_bytes = their bytes (so P_k <= max <
+ * P_{k+1}: the call bisects byte offsets to segment indices).  Other
+ * negative values: MDT_ERR_ARG.  Requires a committed type. */
+MDT_API int mdt_type_iov_len(mdt_type t, mdt_count max_iov_bytes, mdt_count *iov_len,
+                             mdt_count *actual_iov_bytes);
+/* MPIX_Type_iov: segments [iov_offset, iov_offset + max_iov_len) into the
+ * caller-allocated host array iov; *actual_iov_len = how many were written
+ * (0 when iov_offset >= number of segments).  iov_base holds the segment's
+ * byte displacement from the origin, cast to a pointer. */
+MDT_API int mdt_type_iov(mdt_type t, mdt_count iov_offset, mdt_iov *iov, mdt_count max_iov_len,
+                         mdt_count *actual_iov_len);
+
+/* Blocking pack of bytes [inoffset, inoffset + actual) of the packed stream
+ * of (incount x t) read from device buffer inbuf (the origin) into device
+ * buffer outbuf; actual = clamp(incount*size - inoffset, 0, max_pack_bytes),
+ * max_pack_bytes = -1 meaning unlimited.  The work runs on the null stream
+ * and the call returns when it has completed.  Overlapping types pack. */
+MDT_API int mdt_pack(const void *inbuf, mdt_count incount, mdt_type t, mdt_count inoffset, void *outbuf,
+                     mdt_count max_pack_bytes, mdt_count *actual_pack_bytes);
+/* Blocking unpack: writes the insize packed bytes at inbuf into stream
+ * positions [outoffset, outoffset + insize) of (outcount x t) at origin
+ * outbuf.  Bytes outside the typemap are never written.  Errors:
+ * MDT_ERR_TRUNCATE if insize > outcount*size - outoffset, MDT_ERR_OVERLAP
+ * if (outcount x t) has overlapping bytes.  *actual_unpack_bytes = insize. */
+MDT_API int mdt_unpack(const void *inbuf, mdt_count insize, void *outbuf, mdt_count outcount, mdt_type t,
+                       mdt_count outoffset, mdt_count *actual_unpack_bytes);
+
+/* ---------------------------------------------------------------------
+ * Stream-ordered work (Offloading Asynchronous Operations: work enqueued
+ * on a GPU stream runs after earlier work on that stream and before later
+ * work; the host starts it and waits for it separately). */
+/* Wrap a caller-owned HIP stream (NULL = the null stream).  The library
+ * never destroys the HIP stream. */
+MDT_API int mdt_stream_create(mdt_hip_stream s, mdt_stream *out);
+MDT_API int mdt_stream_free(mdt_stream *s);
+/* As mdt_pack / mdt_unpack, but enqueued on stream s; the call returns
+ * immediately (the actual byte count is known from sizes alone).  If req is
+ * not NULL it receives a request that completes with the work. */
+MDT_API int mdt_pack_enqueue(const void *inbuf, mdt_count incount, mdt_type t, mdt_count inoffset,
+                             void *outbuf, mdt_count max_pack_bytes, mdt_count *actual_pack_bytes,
+                             mdt_stream s, mdt_request *req);
+MDT_API int mdt_unpack_enqueue(const void *inbuf, mdt_count insize, void *outbuf, mdt_count outcount,
+                               mdt_type t, mdt_count outoffset, mdt_count *actual_unpack_bytes,
+                               mdt_stream s, mdt_request *req);
+/* Device flatten: write segments [iov_offset, iov_offset + max_iov_len) of
+ * committed type t into the device array dev_iov, each base being
+ * `base` + displacement (base may be NULL for raw displacements); enqueued
+ * on s.  *actual_iov_len is returned immediately. */
+MDT_API int mdt_type_iov_enqueue(mdt_type t, mdt_count iov_offset, mdt_iov *dev_iov, mdt_count max_iov_len,
+                                 const void *base, mdt_count *actual_iov_len, mdt_stream s, mdt_request *req);
+/* Complete a request: mdt_wait blocks; mdt_test sets *flag = 1 and frees
+ * the request if it has completed, else *flag = 0.  Completed requests are
+ * freed and set to MDT_REQUEST_NULL; a NULL request counts as complete. */
+MDT_API int mdt_wait(mdt_request *req);
+MDT_API int mdt_test(mdt_request *req, int *flag);
+MDT_API int mdt_waitall(int n, mdt_request reqs[]);
+
+/* ---------------------------------------------------------------------
+ * Batches: many pack/unpack requests of mixed types and sizes executed by
+ * one persistent kernel launch, captured once in a HIP graph and replayed.
+ * Requests are described on the host; mdt_batch_launch uploads the
+ * descriptors (in stream order) and runs them.  Every request's bytes are
+ * identical to the same request run alone.  Destinations of different
+ * requests must not overlap. */
+MDT_API int mdt_batch_create(mdt_batch *b);
+MDT_API int mdt_batch_free(mdt_batch *b);
+/* Remove all requests (the batch and its captured graph are reused). */
+MDT_API int mdt_batch_clear(mdt_batch b);
+MDT_API int mdt_batch_add_pack(mdt_batch b, const void *inbuf, mdt_count incount, mdt_type t,
+                               mdt_count inoffset, void *outbuf, mdt_count max_pack_bytes,
+                               mdt_count *actual_pack_bytes);
+MDT_API int mdt_batch_add_unpack(mdt_batch b, const void *inbuf, mdt_count insize, void *outbuf,
+                                 mdt_count outcount, mdt_type t, mdt_count outoffset,
+                                 mdt_count *actual_unpack_bytes);
+/* Tuning knobs of the persistent launch.  policy: 0 = static strided split
+ * of tiles over workgroups, 1 = dynamic (atomic tile counter). */
+typedef struct mdt_batch_config {
+    int tile_chunks;    /* 16-byte chunks per workgroup tile: 256, 512, 1024, 2048, 4096 */
+    int wgs_per_cu;     /* persistent workgroups per compute unit, 1..16 */
+    int policy;         /* 0 static, 1 dynamic */
+    int use_graph;      /* 1 = capture and replay a HIP graph, 0 = direct launches */
+} mdt_batch_config;
+MDT_API int mdt_batch_set_config(mdt_batch b, const mdt_batch_config *cfg);
+MDT_API int mdt_batch_get_config(mdt_batch b, mdt_batch_config *cfg);
+/* Time candidate configurations on the batch as it stands (running it
+ * several times; destinations are overwritten with the same bytes) and keep
+ * the fastest.  *best may be NULL. */
+MDT_API int mdt_batch_autotune(mdt_batch b, mdt_stream s, mdt_batch_config *best);
+MDT_API int mdt_batch_launch(mdt_batch b, mdt_stream s, mdt_request *req);
+
+/* ---------------------------------------------------------------------
+ * Serving: a progress engine that continuously batches pack/unpack
+ * requests as they arrive, admits them against a device-memory budget and
+ * runs them on its own HIP streams (General Progress: explicit progress or
+ * a progress thread). */
+typedef struct mdt_server_config {
+    int nstreams;              /* HIP streams the server owns (default 8) */
+    mdt_count budget_bytes;    /* admission budget (default 32 GiB) */
+    int max_batch;             /* requests per launch (default 256) */
+    int max_inflight;          /* launches in flight per stream (default 2) */
+    mdt_count arena_bytes;     /* device arena for packed outputs; 0 = budget_bytes */
+} mdt_server_config;
+typedef struct mdt_server_stats {
+    mdt_count submitted, completed, failed, deferred; /* deferred: admissions that waited */
+    mdt_count bytes;           /* packed bytes moved by completed requests */
+    mdt_count launches;        /* batched kernel launches */
+    double p50_us, p99_us, max_us; /* latency: completion seen by host - submission */
+    double elapsed_s;          /* first submission to last completion */
+    mdt_count inflight_bytes, peak_inflight_bytes;
+} mdt_server_stats;
+MDT_API int mdt_server_create(const mdt_server_config *cfg, mdt_server *out);
+/* Drains every admitted request, stops the progress thread, frees the
+ * server. */
+MDT_API int mdt_server_free(mdt_server *srv);
+/* Submit a pack: bytes [inoffset, inoffset + actual) of (incount x t) at
+ * inbuf into a packed buffer the server allocates from its arena; the
+ * buffer is reported by mdt_server_request_result and released with the
+ * request.  The type must stay valid until the request completes. */
+MDT_API int mdt_server_submit_pack(mdt_server srv, const void *inbuf, mdt_count incount, mdt_type t,
+                                   mdt_count inoffset, mdt_count max_pack_bytes, mdt_request *req);
+/* Submit an unpack of the insize bytes at inbuf into (outcount x t) at
+ * outbuf from stream position outoffset. */
+MDT_API int mdt_server_submit_unpack(mdt_server srv, const void *inbuf, mdt_count insize, void *outbuf,
+                                     mdt_count outcount, mdt_type t, mdt_count outoffset, mdt_request *req);
+/* Server requests: poll with mdt_server_request_test (non-blocking; runs
+ * progress when no progress thread is active), then read the result and
+ * release the request (which returns its arena memory). */
+MDT_API int mdt_server_request_test(mdt_server srv, mdt_request req, int *flag);
+MDT_API int mdt_server_request_wait(mdt_server srv, mdt_request req);
+/* *status: MDT_SUCCESS or the request's error; *packed: the device address
+ * of the packed bytes (pack requests, else NULL); *nbytes: packed bytes;
+ * *latency_us: completion minus submission. */
+MDT_API int mdt_server_request_result(mdt_server srv, mdt_request req, int *status, void **packed,
+                                      mdt_count *nbytes, double *latency_us);
+MDT_API int mdt_server_request_release(mdt_server srv, mdt_request *req);
+/* One round of progress: admit, launch, reap completions (MPIX_Stream_progress). */
+MDT_API int mdt_server_progress(mdt_server srv);
+MDT_API int mdt_server_start_progress_thread(mdt_server srv);
+MDT_API int mdt_server_stop_progress_thread(mdt_server srv);
+MDT_API int mdt_server_stats_get(mdt_server srv, mdt_server_stats *out);
+/* Testing hook: make the next n arena allocations fail (MDT_ERR_NO_MEM is
+ * then reported on those requests only). */
+MDT_API int mdt_server_inject_alloc_failures(mdt_server srv, int n);
+
+/* ---------------------------------------------------------------------
+ * Diagnostics */
+MDT_API const char *mdt_error_string(int code);
+/* The last HIP error code seen by this thread (0 if none). */
+MDT_API int mdt_last_hip_error(void);
+/* Library version as 10000*major + 100*minor + patch. */
+MDT_API int mdt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDT_H */

@@ -1,0 +1,27 @@
+// device.h -- launch interface of the gfx950 kernels (host side).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include "core.h"
+
+namespace mdt {
+
+// One pack or unpack over bytes [off, off + nbytes) of a packed stream.
+struct XferArgs {
+    const uint8_t *typed;  // origin of the typed (non-contiguous) buffer
+    uint8_t *packed;       // first packed byte (stream position off)
+    int64_t off;           // stream position of packed[0]
+    int64_t nbytes;        // packed bytes moved
+    int64_t head;          // packed & 15: the chunk grid is 16-byte aligned
+    int64_t nchunks;       // 16-byte chunks covering [packed, packed + nbytes)
+    int64_t tile_chunks;   // chunks per workgroup tile (0: default)
+};
+
+XferArgs make_args(const void *typed, void *packed, int64_t off, int64_t nbytes);
+int launch_xfer(const DevLayout &L, const XferArgs &A, bool unpack, hipStream_t s);
+int launch_flatten(Compiled *c, DeviceTables *d, int64_t off, int64_t m, mdt_iov *out, const void *base,
+                   hipStream_t s);
+int64_t default_tile_chunks(int64_t nchunks);
+
+}  // namespace mdt

@@ -1,0 +1,283 @@
+// layout_dev.h -- the compiled ("lowered") layout program of a committed
+// datatype, as plain data that both host code and gfx950 kernels read, and
+// the position arithmetic over it.
+//
+// A committed type is lowered to
+//
+//     count loop (stride = extent)
+//       x outer loops (regular, over the whole group list)
+//         x groups (irregular table: displacement, packed length, shape)
+//           x inner loops of the group's shape (regular)
+//             x leaf runs of the shape (contiguous byte runs)
+//
+// which keeps regular layouts O(depth) in size whatever their segment
+// count (Derived Datatypes: a face of an Nx x Ny x Nz array is a two-level
+// strided vector, not Ny*Nz listed segments) and irregular ones O(blocks).
+// A packed-stream byte position is located by one magic-number division
+// per regular level and a directory-guided search over the group table;
+// the same search by run index bisects segments (MPIX_Type_iov_len).
+#pragma once
+
+#include <stdint.h>
+
+#ifdef __HIPCC__
+#include <hip/hip_runtime.h>
+#define MDT_HD __host__ __device__ __forceinline__
+#else
+#define MDT_HD inline
+#endif
+
+namespace mdt {
+
+constexpr int MAXO = 4;   // outer loops
+constexpr int MAXI = 4;   // inner loops per shape
+constexpr int LEAFI = 8;  // leaf runs stored inline in a shape
+
+// n / d for 0 <= n < 2^63 by one 64x64->128 high multiply and a shift
+// (Granlund & Montgomery 1994, "Division by invariant integers using
+// multiplication", round-up variant with N = 63).  d == 1 is flagged.
+struct MagicDiv {
+    uint64_t m;
+    uint32_t s;
+    uint32_t one;
+};
+
+MDT_HD uint64_t mulhi64(uint64_t a, uint64_t b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umul64hi(a, b);
+#else
+    return (uint64_t)(((unsigned __int128)a * b) >> 64);
+#endif
+}
+
+MDT_HD uint64_t magic_div(uint64_t n, const MagicDiv &d)
+{
+    return d.one ? n : (mulhi64(n, d.m) >> d.s);
+}
+
+inline MagicDiv make_magic(uint64_t d)
+{
+    MagicDiv r{0, 0, 0};
+    if (d <= 1) {
+        r.one = 1;
+        return r;
+    }
+    // l = ceil(log2 d); m = ceil(2^(63+l) / d) < 2^64; q = mulhi(n, m) >> (l-1)
+    uint32_t l = 0;
+    while (l < 64 && ((uint64_t)1 << l) < d) l++;
+    unsigned __int128 num = (unsigned __int128)1 << (63 + l);
+    unsigned __int128 m = (num + d - 1) / d;
+    r.m = (uint64_t)m;
+    r.s = l - 1;
+    return r;
+}
+
+struct DevShape {
+    int32_t nloops;     // inner loops, outer to inner
+    int32_t nleaf;      // leaf runs (0 when varlen)
+    int32_t varlen;     // the shape is one run as long as its group
+    int32_t implicit0;  // loop 0's count is the group length / span[0]
+    int64_t unit;       // packed bytes per innermost iteration (sum of leaf lengths)
+    int64_t span[MAXI];    // packed bytes per iteration of loop l
+    int64_t stride[MAXI];  // byte stride of loop l
+    int64_t cnt[MAXI];     // iteration count of loop l (loop 0: see implicit0)
+    int64_t rpi[MAXI];     // runs per iteration of loop l
+    MagicDiv dspan[MAXI];
+    MagicDiv drpi[MAXI];
+    int64_t loff[LEAFI];    // leaf run offsets (inline when nleaf <= LEAFI)
+    int64_t llen[LEAFI];
+    int64_t lpre[LEAFI + 1];  // leaf prefix: lpre[j] = sum of llen[0..j)
+    const int64_t *loff_p;  // leaf arrays when nleaf > LEAFI
+    const int64_t *llen_p;
+    const int64_t *lpre_p;
+};
+
+enum LayoutKind : int32_t {
+    KIND_EMPTY = 0,   // no bytes
+    KIND_CONTIG = 1,  // the packed stream is one contiguous run: addr = base + p
+    KIND_SINGLE = 2,  // one group, no outer loops
+    KIND_MULTI = 3    // group table (optionally under outer loops)
+};
+
+struct DevLayout {
+    int64_t size;     // packed bytes of one element
+    int64_t extent;   // stride between elements of a count
+    MagicDiv dsize;
+    int32_t kind;
+    int32_t nouter;
+    int64_t ospan[MAXO];    // packed bytes per iteration of outer loop l
+    int64_t ostride[MAXO];
+    int64_t ocnt[MAXO];
+    int64_t orun[MAXO];     // runs per iteration of outer loop l
+    MagicDiv dospan[MAXO];
+    MagicDiv dorun[MAXO];
+    int64_t G;              // groups
+    int64_t gsize;          // packed bytes of the whole group list
+    int64_t gruns;          // runs of the whole group list
+    int64_t nruns;          // runs of one element
+    int64_t gdisp0;         // displacement of group 0 (KIND_CONTIG / KIND_SINGLE)
+    int32_t nshapes;
+    int32_t dir_shift;      // directory granularity = 1 << dir_shift packed bytes
+    int64_t ndir;           // directory entries
+    const int64_t *gdisp;   // [G]   group displacement
+    const int64_t *gpre;    // [G+1] packed-byte prefix of groups
+    const int64_t *grpre;   // [G+1] run prefix of groups
+    const int32_t *gshape;  // [G]   shape index (NULL when nshapes == 1)
+    const int32_t *gdir;    // [ndir] group containing byte k << dir_shift of the group list
+    const DevShape *shapes; // [nshapes]
+    DevShape shape0;        // copy of shapes[0]
+};
+
+// Result of locating a packed-stream byte position.
+struct Loc {
+    int64_t addr;  // byte displacement (from the origin) of the located byte
+    int64_t rem;   // bytes left in its run, the located byte included
+};
+
+MDT_HD const int64_t *leaf_off(const DevShape &S) { return S.nleaf > LEAFI ? S.loff_p : S.loff; }
+MDT_HD const int64_t *leaf_len(const DevShape &S) { return S.nleaf > LEAFI ? S.llen_p : S.llen; }
+MDT_HD const int64_t *leaf_pre(const DevShape &S) { return S.nleaf > LEAFI ? S.lpre_p : S.lpre; }
+
+// Position q inside one group of shape S (q < group length glen).
+MDT_HD Loc locate_in_shape(const DevShape &S, uint64_t q, int64_t glen, int64_t addr)
+{
+    Loc r;
+    if (S.varlen) {
+        r.addr = addr + (int64_t)q;
+        r.rem = glen - (int64_t)q;
+        return r;
+    }
+#pragma unroll
+    for (int l = 0; l < MAXI; l++) {
+        if (l < S.nloops) {
+            uint64_t i = magic_div(q, S.dspan[l]);
+            q -= i * (uint64_t)S.span[l];
+            addr += (int64_t)i * S.stride[l];
+        }
+    }
+    const int64_t *pre = leaf_pre(S);
+    int j = 0;
+    if (S.nleaf > 1) {
+        // last j with pre[j] <= q
+        int lo = 0, hi = S.nleaf - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if ((uint64_t)pre[mid] <= q) lo = mid; else hi = mid - 1;
+        }
+        j = lo;
+    }
+    int64_t in = (int64_t)q - pre[j];
+    r.addr = addr + leaf_off(S)[j] + in;
+    r.rem = leaf_len(S)[j] - in;
+    return r;
+}
+
+// Group containing byte q (< gsize) of the group list.
+MDT_HD int64_t find_group(const DevLayout &L, uint64_t q)
+{
+    int64_t k = (int64_t)(q >> L.dir_shift);
+    int64_t lo = L.gdir[k];
+    int64_t hi = (k + 1 < L.ndir) ? L.gdir[k + 1] : L.G - 1;
+    while (lo < hi) {
+        int64_t mid = (lo + hi + 1) >> 1;
+        if ((uint64_t)L.gpre[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Locate stream byte p (0 <= p < count*size) of (count x type).
+template <int KIND>
+MDT_HD Loc locate(const DevLayout &L, uint64_t p)
+{
+    Loc r;
+    if (KIND == KIND_CONTIG) {
+        r.addr = L.gdisp0 + (int64_t)p;
+        r.rem = INT64_MAX;
+        return r;
+    }
+    uint64_t e = magic_div(p, L.dsize);
+    uint64_t q = p - e * (uint64_t)L.size;
+    int64_t addr = (int64_t)e * L.extent;
+    if (KIND == KIND_SINGLE) {
+        r = locate_in_shape(L.shape0, q, L.size, addr + L.gdisp0);
+        return r;
+    }
+#pragma unroll
+    for (int l = 0; l < MAXO; l++) {
+        if (l < L.nouter) {
+            uint64_t i = magic_div(q, L.dospan[l]);
+            q -= i * (uint64_t)L.ospan[l];
+            addr += (int64_t)i * L.ostride[l];
+        }
+    }
+    int64_t g = find_group(L, q);
+    int64_t g0 = L.gpre[g];
+    int64_t glen = L.gpre[g + 1] - g0;
+    const DevShape &S = L.nshapes == 1 ? L.shape0 : L.shapes[L.gshape[g]];
+    return locate_in_shape(S, q - (uint64_t)g0, glen, addr + L.gdisp[g]);
+}
+
+MDT_HD Loc locate_any(const DevLayout &L, uint64_t p)
+{
+    switch (L.kind) {
+    case KIND_CONTIG: return locate<KIND_CONTIG>(L, p);
+    case KIND_SINGLE: return locate<KIND_SINGLE>(L, p);
+    default: return locate<KIND_MULTI>(L, p);
+    }
+}
+
+// Run number k (0 <= k < nruns) of one element: its displacement and length.
+struct RunInfo {
+    int64_t addr;
+    int64_t len;
+};
+
+MDT_HD RunInfo run_at(const DevLayout &L, uint64_t k)
+{
+    RunInfo r;
+    int64_t addr = 0;
+    const DevShape *S;
+    int64_t glen;
+    if (L.kind == KIND_CONTIG || L.kind == KIND_SINGLE) {
+        S = &L.shape0;
+        addr = L.gdisp0;
+        glen = L.size;
+    } else {
+#pragma unroll
+        for (int l = 0; l < MAXO; l++) {
+            if (l < L.nouter) {
+                uint64_t i = magic_div(k, L.dorun[l]);
+                k -= i * (uint64_t)L.orun[l];
+                addr += (int64_t)i * L.ostride[l];
+            }
+        }
+        int64_t lo = 0, hi = L.G - 1;
+        while (lo < hi) {
+            int64_t mid = (lo + hi + 1) >> 1;
+            if ((uint64_t)L.grpre[mid] <= k) lo = mid; else hi = mid - 1;
+        }
+        k -= (uint64_t)L.grpre[lo];
+        addr += L.gdisp[lo];
+        glen = L.gpre[lo + 1] - L.gpre[lo];
+        S = L.nshapes == 1 ? &L.shape0 : &L.shapes[L.gshape[lo]];
+    }
+    if (S->varlen) {
+        r.addr = addr;
+        r.len = glen;
+        return r;
+    }
+#pragma unroll
+    for (int l = 0; l < MAXI; l++) {
+        if (l < S->nloops) {
+            uint64_t i = magic_div(k, S->drpi[l]);
+            k -= i * (uint64_t)S->rpi[l];
+            addr += (int64_t)i * S->stride[l];
+        }
+    }
+    r.addr = addr + leaf_off(*S)[k];
+    r.len = leaf_len(*S)[k];
+    return r;
+}
+
+}  // namespace mdt

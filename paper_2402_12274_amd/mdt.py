@@ -1,0 +1,347 @@
+"""ctypes binding of libmdt.so (C ABI in include/mdt.h).
+
+Argument marshalling only: every step of type compilation, segment queries
+and data movement runs in the native library and its gfx950 kernels.  The
+functions keep the C names; ``Type`` is a small owning wrapper around a type
+handle and ``build_type`` turns an input spec (see ``inputs``) into one.
+
+Importing this module loads the library and raises ImportError when it has
+not been built (``python -m paper_2402_12274_amd.build``): there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmdt.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2402_12274_amd.build`")
+
+_lib = C.CDLL(LIB_PATH)
+
+# error codes (include/mdt.h)
+SUCCESS, ERR_ARG, ERR_TYPE, ERR_COUNT, ERR_TRUNCATE, ERR_OVERLAP, ERR_NO_MEM, ERR_HIP, ERR_AGAIN, ERR_STATE = range(10)
+ORDER_C, ORDER_FORTRAN = 0, 1
+BASIC_CODES = {
+    "BYTE": 0, "CHAR": 1, "INT8": 2, "UINT8": 3, "INT16": 4, "UINT16": 5, "INT32": 6, "UINT32": 7,
+    "INT": 8, "FLOAT": 9, "INT64": 10, "UINT64": 11, "DOUBLE": 12,
+}
+
+_P = C.c_void_p
+_I64 = C.c_int64
+_I64P = C.POINTER(C.c_int64)
+_INT = C.c_int
+
+
+class Iov(C.Structure):
+    _fields_ = [("iov_base", C.c_void_p), ("iov_len", C.c_int64)]
+
+
+class BatchConfig(C.Structure):
+    _fields_ = [("tile_chunks", C.c_int), ("wgs_per_cu", C.c_int), ("policy", C.c_int), ("use_graph", C.c_int)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("nstreams", C.c_int), ("budget_bytes", C.c_int64), ("max_batch", C.c_int),
+                ("max_inflight", C.c_int), ("arena_bytes", C.c_int64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("deferred", C.c_int64), ("bytes", C.c_int64), ("launches", C.c_int64),
+                ("p50_us", C.c_double), ("p99_us", C.c_double), ("max_us", C.c_double),
+                ("elapsed_s", C.c_double), ("inflight_bytes", C.c_int64), ("peak_inflight_bytes", C.c_int64)]
+
+
+_SIGS = {
+    "mdt_basic": ([_INT], _P),
+    "mdt_type_contiguous": ([_I64, _P, C.POINTER(_P)], _INT),
+    "mdt_type_vector": ([_I64, _I64, _I64, _P, C.POINTER(_P)], _INT),
+    "mdt_type_create_hvector": ([_I64, _I64, _I64, _P, C.POINTER(_P)], _INT),
+    "mdt_type_indexed": ([_I64, _I64P, _I64P, _P, C.POINTER(_P)], _INT),
+    "mdt_type_create_hindexed": ([_I64, _I64P, _I64P, _P, C.POINTER(_P)], _INT),
+    "mdt_type_create_indexed_block": ([_I64, _I64, _I64P, _P, C.POINTER(_P)], _INT),
+    "mdt_type_create_hindexed_block": ([_I64, _I64, _I64P, _P, C.POINTER(_P)], _INT),
+    "mdt_type_create_struct": ([_I64, _I64P, _I64P, C.POINTER(_P), C.POINTER(_P)], _INT),
+    "mdt_type_create_subarray": ([_INT, _I64P, _I64P, _I64P, _INT, _P, C.POINTER(_P)], _INT),
+    "mdt_type_create_resized": ([_P, _I64, _I64, C.POINTER(_P)], _INT),
+    "mdt_type_dup": ([_P, C.POINTER(_P)], _INT),
+    "mdt_type_commit": ([C.POINTER(_P)], _INT),
+    "mdt_type_free": ([C.POINTER(_P)], _INT),
+    "mdt_type_size": ([_P, _I64P], _INT),
+    "mdt_type_get_extent": ([_P, _I64P, _I64P], _INT),
+    "mdt_type_get_true_extent": ([_P, _I64P, _I64P], _INT),
+    "mdt_type_iov_len": ([_P, _I64, _I64P, _I64P], _INT),
+    "mdt_type_iov": ([_P, _I64, C.POINTER(Iov), _I64, _I64P], _INT),
+    "mdt_pack": ([_P, _I64, _P, _I64, _P, _I64, _I64P], _INT),
+    "mdt_unpack": ([_P, _I64, _P, _I64, _P, _I64, _I64P], _INT),
+    "mdt_stream_create": ([_P, C.POINTER(_P)], _INT),
+    "mdt_stream_free": ([C.POINTER(_P)], _INT),
+    "mdt_pack_enqueue": ([_P, _I64, _P, _I64, _P, _I64, _I64P, _P, C.POINTER(_P)], _INT),
+    "mdt_unpack_enqueue": ([_P, _I64, _P, _I64, _P, _I64, _I64P, _P, C.POINTER(_P)], _INT),
+    "mdt_type_iov_enqueue": ([_P, _I64, _P, _I64, _P, _I64P, _P, C.POINTER(_P)], _INT),
+    "mdt_wait": ([C.POINTER(_P)], _INT),
+    "mdt_test": ([C.POINTER(_P), C.POINTER(_INT)], _INT),
+    "mdt_waitall": ([_INT, C.POINTER(_P)], _INT),
+    "mdt_batch_create": ([C.POINTER(_P)], _INT),
+    "mdt_batch_free": ([C.POINTER(_P)], _INT),
+    "mdt_batch_clear": ([_P], _INT),
+    "mdt_batch_add_pack": ([_P, _P, _I64, _P, _I64, _P, _I64, _I64P], _INT),
+    "mdt_batch_add_unpack": ([_P, _P, _I64, _P, _I64, _P, _I64, _I64P], _INT),
+    "mdt_batch_set_config": ([_P, C.POINTER(BatchConfig)], _INT),
+    "mdt_batch_get_config": ([_P, C.POINTER(BatchConfig)], _INT),
+    "mdt_batch_autotune": ([_P, _P, C.POINTER(BatchConfig)], _INT),
+    "mdt_batch_launch": ([_P, _P, C.POINTER(_P)], _INT),
+    "mdt_server_create": ([C.POINTER(ServerConfig), C.POINTER(_P)], _INT),
+    "mdt_server_free": ([C.POINTER(_P)], _INT),
+    "mdt_server_submit_pack": ([_P, _P, _I64, _P, _I64, _I64, C.POINTER(_P)], _INT),
+    "mdt_server_submit_unpack": ([_P, _P, _I64, _P, _I64, _P, _I64, C.POINTER(_P)], _INT),
+    "mdt_server_request_test": ([_P, _P, C.POINTER(_INT)], _INT),
+    "mdt_server_request_wait": ([_P, _P], _INT),
+    "mdt_server_request_result": ([_P, _P, C.POINTER(_INT), C.POINTER(_P), _I64P, C.POINTER(C.c_double)], _INT),
+    "mdt_server_request_release": ([_P, C.POINTER(_P)], _INT),
+    "mdt_server_progress": ([_P], _INT),
+    "mdt_server_start_progress_thread": ([_P], _INT),
+    "mdt_server_stop_progress_thread": ([_P], _INT),
+    "mdt_server_stats_get": ([_P, C.POINTER(ServerStats)], _INT),
+    "mdt_server_inject_alloc_failures": ([_P, _INT], _INT),
+    "mdt_error_string": ([_INT], C.c_char_p),
+    "mdt_last_hip_error": ([], _INT),
+    "mdt_version": ([], _INT),
+}
+
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name, None)
+    if _f is not None:
+        _f.argtypes = _args
+        _f.restype = _res
+
+SYMBOLS = tuple(_SIGS)
+
+
+class MdtError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        msg = _lib.mdt_error_string(code).decode()
+        if code == ERR_HIP:
+            msg += f" (hip error {_lib.mdt_last_hip_error()})"
+        super().__init__(f"{what}: {msg} [{code}]")
+        self.code = code
+
+
+def check(rc: int, what: str = "mdt"):
+    if rc != SUCCESS:
+        raise MdtError(rc, what)
+
+
+def _arr(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int64))
+    return a, a.ctypes.data_as(_I64P)
+
+
+def lib():
+    return _lib
+
+
+# ---------------------------------------------------------------------------
+# types
+
+
+class Type:
+    """Owning wrapper of an mdt_type handle."""
+
+    def __init__(self, handle: int, owned: bool = True):
+        self.handle = handle
+        self.owned = owned
+
+    def __del__(self):
+        if getattr(self, "owned", False) and self.handle:
+            h = _P(self.handle)
+            _lib.mdt_type_free(C.byref(h))
+            self.handle = None
+
+    @property
+    def h(self):
+        return _P(self.handle)
+
+    def commit(self) -> "Type":
+        h = _P(self.handle)
+        check(_lib.mdt_type_commit(C.byref(h)), "commit")
+        return self
+
+    def size(self) -> int:
+        v = C.c_int64()
+        check(_lib.mdt_type_size(self.h, C.byref(v)), "size")
+        return v.value
+
+    def extent(self):
+        a, b = C.c_int64(), C.c_int64()
+        check(_lib.mdt_type_get_extent(self.h, C.byref(a), C.byref(b)), "extent")
+        return a.value, b.value
+
+    def true_extent(self):
+        a, b = C.c_int64(), C.c_int64()
+        check(_lib.mdt_type_get_true_extent(self.h, C.byref(a), C.byref(b)), "true_extent")
+        return a.value, b.value
+
+    def iov_len(self, max_iov_bytes: int):
+        a, b = C.c_int64(), C.c_int64()
+        check(_lib.mdt_type_iov_len(self.h, max_iov_bytes, C.byref(a), C.byref(b)), "iov_len")
+        return a.value, b.value
+
+    def iov(self, iov_offset: int, max_iov_len: int):
+        m = max(0, max_iov_len)
+        buf = (Iov * max(1, m))()
+        got = C.c_int64()
+        check(_lib.mdt_type_iov(self.h, iov_offset, buf, max_iov_len, C.byref(got)), "iov")
+        n = got.value
+        base = np.array([(buf[i].iov_base or 0) for i in range(n)], dtype=np.uint64).view(np.int64)
+        ln = np.array([buf[i].iov_len for i in range(n)], dtype=np.int64)
+        return base, ln
+
+
+def basic(name: str) -> Type:
+    return Type(_lib.mdt_basic(BASIC_CODES[name]), owned=False)
+
+
+def _new(fn, *args, what="constructor") -> Type:
+    out = _P()
+    check(fn(*args, C.byref(out)), what)
+    return Type(out.value)
+
+
+def build_type(spec, commit: bool = True) -> Type:
+    """Build (and commit) a type from an input spec (nested constructor tuples)."""
+    t = _build(spec)
+    if commit:
+        t.commit()
+    return t
+
+
+def _build(spec) -> Type:
+    k = spec[0]
+    if k == "basic":
+        return basic(spec[1])
+    if k == "contiguous":
+        c = _build(spec[2])
+        return _new(_lib.mdt_type_contiguous, spec[1], c.h, what=k)
+    if k == "vector":
+        _, n, bl, st, child = spec
+        c = _build(child)
+        return _new(_lib.mdt_type_vector, n, bl, st, c.h, what=k)
+    if k == "hvector":
+        _, n, bl, st, child = spec
+        c = _build(child)
+        return _new(_lib.mdt_type_create_hvector, n, bl, st, c.h, what=k)
+    if k in ("indexed", "hindexed"):
+        _, bls, disps, child = spec
+        c = _build(child)
+        b, bp = _arr(bls)
+        d, dp = _arr(disps)
+        f = _lib.mdt_type_indexed if k == "indexed" else _lib.mdt_type_create_hindexed
+        return _new(f, b.size, bp, dp, c.h, what=k)
+    if k in ("indexed_block", "hindexed_block"):
+        _, bl, disps, child = spec
+        c = _build(child)
+        d, dp = _arr(disps)
+        f = _lib.mdt_type_create_indexed_block if k == "indexed_block" else _lib.mdt_type_create_hindexed_block
+        return _new(f, d.size, bl, dp, c.h, what=k)
+    if k == "struct":
+        _, bls, disps, children = spec
+        kids = [_build(x) for x in children]
+        b, bp = _arr(bls)
+        d, dp = _arr(disps)
+        arr = (_P * max(1, len(kids)))(*[x.handle for x in kids])
+        return _new(_lib.mdt_type_create_struct, b.size, bp, dp, arr, what=k)
+    if k == "subarray":
+        _, sizes, subs, starts, order, child = spec
+        c = _build(child)
+        s, sp = _arr(sizes)
+        u, up = _arr(subs)
+        t, tp = _arr(starts)
+        o = {"C": ORDER_C, "F": ORDER_FORTRAN}.get(order, 7)
+        return _new(_lib.mdt_type_create_subarray, s.size, sp, up, tp, o, c.h, what=k)
+    if k == "resized":
+        _, lb, ext, child = spec
+        c = _build(child)
+        return _new(_lib.mdt_type_create_resized, c.h, lb, ext, what=k)
+    if k == "dup":
+        c = _build(spec[1])
+        return _new(_lib.mdt_type_dup, c.h, what=k)
+    raise ValueError(f"unknown constructor {k!r}")
+
+
+# ---------------------------------------------------------------------------
+# data movement (device pointers as ints)
+
+
+def mdt_pack(inbuf: int, incount: int, t: Type, inoffset: int, outbuf: int, max_pack_bytes: int = -1) -> int:
+    n = C.c_int64()
+    check(_lib.mdt_pack(_P(inbuf), incount, t.h, inoffset, _P(outbuf), max_pack_bytes, C.byref(n)), "mdt_pack")
+    return n.value
+
+
+def mdt_unpack(inbuf: int, insize: int, outbuf: int, outcount: int, t: Type, outoffset: int = 0) -> int:
+    n = C.c_int64()
+    check(_lib.mdt_unpack(_P(inbuf), insize, _P(outbuf), outcount, t.h, outoffset, C.byref(n)), "mdt_unpack")
+    return n.value
+
+
+class Stream:
+    """mdt_stream wrapping a HIP stream handle (int; 0 = null stream)."""
+
+    def __init__(self, hip_stream: int = 0):
+        self.handle = _P()
+        check(_lib.mdt_stream_create(_P(hip_stream), C.byref(self.handle)), "stream_create")
+
+    def __del__(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            _lib.mdt_stream_free(C.byref(self.handle))
+
+    @property
+    def h(self):
+        return self.handle
+
+
+class Request:
+    def __init__(self):
+        self.handle = _P()
+
+    def wait(self):
+        check(_lib.mdt_wait(C.byref(self.handle)), "wait")
+
+    def test(self) -> bool:
+        f = C.c_int()
+        check(_lib.mdt_test(C.byref(self.handle), C.byref(f)), "test")
+        return bool(f.value)
+
+
+def mdt_pack_enqueue(inbuf: int, incount: int, t: Type, inoffset: int, outbuf: int, max_pack_bytes: int,
+                     stream: Stream, want_request: bool = False):
+    n = C.c_int64()
+    req = Request() if want_request else None
+    check(_lib.mdt_pack_enqueue(_P(inbuf), incount, t.h, inoffset, _P(outbuf), max_pack_bytes, C.byref(n), stream.h,
+                                C.byref(req.handle) if req else None), "mdt_pack_enqueue")
+    return n.value, req
+
+
+def mdt_unpack_enqueue(inbuf: int, insize: int, outbuf: int, outcount: int, t: Type, outoffset: int,
+                       stream: Stream, want_request: bool = False):
+    n = C.c_int64()
+    req = Request() if want_request else None
+    check(_lib.mdt_unpack_enqueue(_P(inbuf), insize, _P(outbuf), outcount, t.h, outoffset, C.byref(n), stream.h,
+                                  C.byref(req.handle) if req else None), "mdt_unpack_enqueue")
+    return n.value, req
+
+
+def mdt_type_iov_enqueue(t: Type, iov_offset: int, dev_iov: int, max_iov_len: int, base: int, stream: Stream,
+                         want_request: bool = False):
+    n = C.c_int64()
+    req = Request() if want_request else None
+    check(_lib.mdt_type_iov_enqueue(t.h, iov_offset, _P(dev_iov), max_iov_len, _P(base), C.byref(n), stream.h,
+                                    C.byref(req.handle) if req else None), "mdt_type_iov_enqueue")
+    return n.value, req

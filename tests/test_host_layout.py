@@ -1,0 +1,138 @@
+"""Host logic of libmdt (no GPU needed): constructors, attributes, commit,
+and the segment queries mdt_type_iov_len / mdt_type_iov, compared with the
+oracle on the same specs -- random tiny types of every constructor and the
+workload layouts at full size.  Also checks that regular layouts compile to
+a description whose size does not grow with the segment count."""
+import numpy as np
+import pytest
+
+import bruteforce as bf
+from oracle import build_type as obuild
+from paper_2402_12274_amd import inputs
+from typegen import tiny_specs
+
+mdt = pytest.importorskip("paper_2402_12274_amd.mdt")
+
+
+def _cmp_attrs(t, o):
+    a = o.attrs()
+    assert t.size() == a["size"]
+    assert t.extent() == (a["lb"], a["extent"])
+    assert t.true_extent() == (a["true_lb"], a["true_extent"])
+
+
+def _cmp_segments(t, o, probe_all=True):
+    nseg, size = o.iov_len(-1)
+    assert t.iov_len(-1) == (nseg, size)
+    ob, ol = o.iov(0, nseg)
+    tb, tl = t.iov(0, nseg + 2)
+    assert np.array_equal(tb, ob) and np.array_equal(tl, ol)
+    if probe_all:
+        for mb in range(0, size + 2):
+            assert t.iov_len(mb) == o.iov_len(mb), mb
+    else:
+        g = np.random.Generator(np.random.PCG64(nseg))
+        for mb in list(g.integers(0, size + 1, 200)) + [0, size - 1, size, size + 1]:
+            assert t.iov_len(int(mb)) == o.iov_len(int(mb)), mb
+    for off in (0, 1, nseg // 2, max(nseg - 1, 0), nseg, nseg + 3):
+        for m in (0, 1, 3, 17):
+            b1, l1 = t.iov(off, m)
+            b2, l2 = o.iov(off, m)
+            assert np.array_equal(b1, b2) and np.array_equal(l1, l2)
+
+
+SPECS = tiny_specs(4242, 200)
+
+
+@pytest.mark.parametrize("i", range(len(SPECS)))
+def test_random_types_match_oracle(i):
+    spec = SPECS[i]
+    t = mdt.build_type(spec)
+    o = obuild(spec)
+    _cmp_attrs(t, o)
+    _cmp_segments(t, o)
+
+
+def test_workload_types_match_oracle():
+    specs = [inputs.vector_small(), inputs.particle_struct()]
+    specs += [s for _, s in inputs.halo_faces(512)]
+    for spec in specs:
+        t = mdt.build_type(spec)
+        o = obuild(spec)
+        _cmp_attrs(t, o)
+        _cmp_segments(t, o, probe_all=False)
+
+
+def test_hindexed_workload_matches_oracle():
+    lens, disps = inputs.hindexed_blocks(nblocks=100_000, span=1 << 26, seed=7)
+    spec = inputs.hindexed_type(lens, disps)
+    t = mdt.build_type(spec)
+    o = obuild(spec)
+    _cmp_attrs(t, o)
+    _cmp_segments(t, o, probe_all=False)
+
+
+def test_worked_example_through_library():
+    import json
+    import os
+
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "typeiov_example.json")))
+    t = mdt.build_type(g["spec"])
+    assert t.iov_len(g["max_iov_bytes"]) == (g["iov_len"], g["actual_iov_bytes"])
+    b, ln = t.iov(0, 4)
+    assert b.tolist() == g["iov_base"] and ln.tolist() == g["iov_len_each"]
+    assert t.extent() == (g["lb"], g["extent"])
+    assert t.true_extent() == (g["true_lb"], g["true_extent"])
+
+
+def test_errors():
+    D = inputs.DOUBLE
+    t = mdt.build_type(("vector", 4, 1, 2, D))
+    with pytest.raises(mdt.MdtError) as e:
+        t.iov_len(-2)
+    assert e.value.code == mdt.ERR_ARG
+    u = mdt.build_type(("vector", 4, 1, 2, D), commit=False)
+    with pytest.raises(mdt.MdtError) as e:
+        u.iov_len(-1)
+    assert e.value.code == mdt.ERR_TYPE
+    assert u.size() == 32  # attributes work before commit
+    for bad in [("subarray", [4], [5], [0], "C", D), ("subarray", [4], [2], [3], "C", D),
+                ("vector", -1, 1, 1, D), ("hindexed", [1, -1], [0, 8], D),
+                ("vector", 2, 1, 2 ** 62, ("vector", 2, 1, 2 ** 62, D))]:
+        with pytest.raises(mdt.MdtError) as e:
+            mdt.build_type(bad)
+        assert e.value.code == mdt.ERR_ARG
+    # freed handle
+    h = mdt._P(t.handle)
+    mdt.check(mdt.lib().mdt_type_free(mdt.C.byref(h)))
+    t.owned = False
+    assert h.value is None
+
+
+def test_children_outlive_free():
+    D = inputs.DOUBLE
+    c = mdt.build_type(("vector", 3, 1, 2, D), commit=False)
+    out = mdt._P()
+    mdt.check(mdt.lib().mdt_type_contiguous(4, c.h, mdt.C.byref(out)))
+    parent = mdt.Type(out.value)
+    del c  # frees the caller's reference to the child
+    parent.commit()
+    assert parent.size() == 96
+    # each copy's last element ends where the next copy's first begins, so
+    # 12 runs merge into 9 segments
+    assert parent.iov_len(-1) == obuild(("contiguous", 4, ("vector", 3, 1, 2, D))).iov_len(-1) == (9, 96)
+
+
+def test_regular_layout_description_is_constant_size():
+    # The YZ-surface argument: the segment count grows as N^2 but the
+    # compiled description does not (no per-segment table is built).
+    import ctypes
+
+    for n in (64, 256, 1024):
+        t = mdt.build_type(("subarray", [n, n, n], [n, n, 1], [0, 0, 0], "C", inputs.DOUBLE))
+        assert t.iov_len(-1) == (n * n, n * n * 8)
+    # the face of a 1024^3 array (1M segments) commits and answers a query
+    # deep inside it by position arithmetic
+    b, ln = t.iov(n * n - 1, 1)
+    assert b[0] == ((n - 1) * n * n + (n - 1) * n) * 8 and ln[0] == 8
+    assert ctypes.sizeof(mdt.Iov) == 16
