@@ -345,3 +345,130 @@ def mdt_type_iov_enqueue(t: Type, iov_offset: int, dev_iov: int, max_iov_len: in
     check(_lib.mdt_type_iov_enqueue(t.h, iov_offset, _P(dev_iov), max_iov_len, _P(base), C.byref(n), stream.h,
                                     C.byref(req.handle) if req else None), "mdt_type_iov_enqueue")
     return n.value, req
+
+
+# ---------------------------------------------------------------------------
+# batches
+
+
+class Batch:
+    """mdt_batch: many requests in one persistent (graph-captured) launch."""
+
+    def __init__(self):
+        self.handle = _P()
+        check(_lib.mdt_batch_create(C.byref(self.handle)), "batch_create")
+        self._keep = []
+
+    def __del__(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            _lib.mdt_batch_free(C.byref(self.handle))
+
+    def clear(self):
+        check(_lib.mdt_batch_clear(self.handle), "batch_clear")
+        self._keep = []
+
+    def add_pack(self, inbuf: int, incount: int, t: Type, inoffset: int, outbuf: int, max_pack_bytes: int = -1):
+        n = C.c_int64()
+        check(_lib.mdt_batch_add_pack(self.handle, _P(inbuf), incount, t.h, inoffset, _P(outbuf), max_pack_bytes,
+                                      C.byref(n)), "batch_add_pack")
+        self._keep.append(t)
+        return n.value
+
+    def add_unpack(self, inbuf: int, insize: int, outbuf: int, outcount: int, t: Type, outoffset: int = 0):
+        n = C.c_int64()
+        check(_lib.mdt_batch_add_unpack(self.handle, _P(inbuf), insize, _P(outbuf), outcount, t.h, outoffset,
+                                        C.byref(n)), "batch_add_unpack")
+        self._keep.append(t)
+        return n.value
+
+    def set_config(self, cfg: BatchConfig):
+        check(_lib.mdt_batch_set_config(self.handle, C.byref(cfg)), "batch_set_config")
+
+    def get_config(self) -> BatchConfig:
+        cfg = BatchConfig()
+        check(_lib.mdt_batch_get_config(self.handle, C.byref(cfg)), "batch_get_config")
+        return cfg
+
+    def autotune(self, stream: Stream) -> BatchConfig:
+        cfg = BatchConfig()
+        check(_lib.mdt_batch_autotune(self.handle, stream.h, C.byref(cfg)), "batch_autotune")
+        return cfg
+
+    def launch(self, stream: Stream, want_request: bool = False):
+        req = Request() if want_request else None
+        check(_lib.mdt_batch_launch(self.handle, stream.h, C.byref(req.handle) if req else None), "batch_launch")
+        return req
+
+
+def config_dict(cfg: BatchConfig) -> dict:
+    return {f: getattr(cfg, f) for f, _ in cfg._fields_}
+
+
+# ---------------------------------------------------------------------------
+# serving
+
+
+class Server:
+    """mdt_server: continuous batching of pack/unpack requests."""
+
+    def __init__(self, nstreams=8, budget_bytes=32 << 30, max_batch=256, max_inflight=2, arena_bytes=0):
+        cfg = ServerConfig(nstreams, budget_bytes, max_batch, max_inflight, arena_bytes)
+        self.handle = _P()
+        check(_lib.mdt_server_create(C.byref(cfg), C.byref(self.handle)), "server_create")
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            check(_lib.mdt_server_free(C.byref(self.handle)), "server_free")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit_pack(self, inbuf: int, incount: int, t: Type, inoffset: int = 0, max_pack_bytes: int = -1) -> int:
+        r = _P()
+        check(_lib.mdt_server_submit_pack(self.handle, _P(inbuf), incount, t.h, inoffset, max_pack_bytes,
+                                          C.byref(r)), "server_submit_pack")
+        return r.value
+
+    def submit_unpack(self, inbuf: int, insize: int, outbuf: int, outcount: int, t: Type, outoffset: int = 0) -> int:
+        r = _P()
+        check(_lib.mdt_server_submit_unpack(self.handle, _P(inbuf), insize, _P(outbuf), outcount, t.h, outoffset,
+                                            C.byref(r)), "server_submit_unpack")
+        return r.value
+
+    def test(self, req: int) -> bool:
+        f = C.c_int()
+        check(_lib.mdt_server_request_test(self.handle, _P(req), C.byref(f)), "server_request_test")
+        return bool(f.value)
+
+    def wait(self, req: int):
+        check(_lib.mdt_server_request_wait(self.handle, _P(req)), "server_request_wait")
+
+    def result(self, req: int):
+        st, pk, nb, lat = C.c_int(), _P(), C.c_int64(), C.c_double()
+        check(_lib.mdt_server_request_result(self.handle, _P(req), C.byref(st), C.byref(pk), C.byref(nb),
+                                             C.byref(lat)), "server_request_result")
+        return st.value, (pk.value or 0), nb.value, lat.value
+
+    def release(self, req: int):
+        r = _P(req)
+        check(_lib.mdt_server_request_release(self.handle, C.byref(r)), "server_request_release")
+
+    def progress(self):
+        check(_lib.mdt_server_progress(self.handle), "server_progress")
+
+    def start(self):
+        check(_lib.mdt_server_start_progress_thread(self.handle), "start_progress_thread")
+
+    def stop(self):
+        check(_lib.mdt_server_stop_progress_thread(self.handle), "stop_progress_thread")
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        check(_lib.mdt_server_stats_get(self.handle, C.byref(s)), "server_stats")
+        return {f: getattr(s, f) for f, _ in s._fields_}
+
+    def inject_alloc_failures(self, n: int):
+        check(_lib.mdt_server_inject_alloc_failures(self.handle, n), "inject")

@@ -1,0 +1,244 @@
+"""Stream order, requests, batched launches and the serving loop on the GPU.
+
+- enqueue semantics: an enqueued pack is visible to later work on the same
+  stream with no host synchronisation in between; requests complete;
+- batches: every request of a mixed batch (vectors, halo faces, hindexed;
+  sizes log-uniform) gives the bytes of the same request run alone, for both
+  split policies, with and without graph capture, across graph replays with
+  eager work in between and after the descriptors change; the autotuner
+  returns a valid configuration;
+- serving: mixed pack/unpack requests served with continuous batching equal
+  the same requests run alone; a tiny budget defers but does not fail;
+  injected arena failures fail exactly those requests; shutdown drains.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import first_diff, note, to_dev, to_host, zeros_dev
+from oracle import build_type as obuild
+from paper_2402_12274_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    from gpu_util import torch_cuda
+
+    torch = torch_cuda()
+    from paper_2402_12274_amd import mdt
+
+    return torch, mdt
+
+
+def test_enqueue_stream_order(env):
+    torch, mdt = env
+    note("enqueue stream order")
+    spec = inputs.halo_face(128, 2, 2, "lo")
+    t = mdt.build_type(spec)
+    o = obuild(spec)
+    host = inputs.random_bytes(128 ** 3 * 8, seed=31)
+    side = torch.cuda.Stream()
+    ms = mdt.Stream(side.cuda_stream)
+    src = torch.zeros(host.size, dtype=torch.uint8, device="cuda")
+    pinned = torch.from_numpy(host).pin_memory()
+    out = torch.zeros(t.size(), dtype=torch.uint8, device="cuda")
+    with torch.cuda.stream(side):
+        src.copy_(pinned, non_blocking=True)          # producer on the stream
+        n, req = mdt.mdt_pack_enqueue(src.data_ptr(), 1, t, 0, out.data_ptr(), -1, ms, want_request=True)
+        snap = out.clone()                             # consumer on the same stream
+        back = torch.zeros_like(src)
+        m, req2 = mdt.mdt_unpack_enqueue(snap.data_ptr(), n, back.data_ptr(), 1, t, 0, ms, want_request=True)
+    assert n == m == t.size()
+    req.wait()
+    while not req2.test():
+        pass
+    side.synchronize()
+    ref = o.pack(host, 0, 1)
+    assert first_diff(to_host(snap), ref) is None
+    exp = np.zeros_like(host)
+    o.unpack(ref, exp, 0, 1)
+    assert first_diff(to_host(back), exp) is None
+
+
+def _mix(nreq, seed, n_face=128, vec_count=1 << 14, hi=1 << 20):
+    reqs = inputs.batch_mix(nreq=nreq, seed=seed, hi=hi, n_face=n_face, vec_count=vec_count)
+    lens, disps = inputs.hindexed_blocks(nblocks=20000, span=1 << 24, seed=seed + 1)
+    hspec = inputs.hindexed_type(lens, disps)
+    return reqs, hspec
+
+
+def _arena_bytes(kind, n_face, vec_count):
+    if kind == "vector":
+        return vec_count * 64 * 8
+    if kind == "face":
+        return n_face ** 3 * 8
+    return 1 << 24
+
+
+def test_batch_equals_alone(env):
+    torch, mdt = env
+    n_face, vec_count = 128, 1 << 14
+    reqs, hspec = _mix(300, 77, n_face, vec_count)
+    arenas = {k: to_dev(inputs.random_bytes(_arena_bytes(k, n_face, vec_count), seed=40 + i))
+              for i, k in enumerate(("vector", "face", "hindexed"))}
+    cache = {}
+
+    def ty(r):
+        key = r["spec_key"]
+        if key not in cache:
+            cache[key] = mdt.build_type(r["spec"] if r["spec"] is not None else hspec)
+        return cache[key]
+
+    plan = []
+    for r in reqs:
+        t = ty(r)
+        n = min(r["target"], t.size())
+        plan.append((t, arenas[r["kind"]], n))
+    total = sum(n for _, _, n in plan)
+    offs = np.concatenate([[0], np.cumsum([n + 16 for _, _, n in plan])])
+    alone = zeros_dev(int(offs[-1]), 0)
+    for (t, src, n), o in zip(plan, offs):
+        mdt.mdt_pack(src.data_ptr(), 1, t, 0, alone.data_ptr() + int(o) + 3, n)
+    ref = to_host(alone)
+    # sampled requests against the oracle as well
+    for i in range(0, len(plan), 37):
+        t, src, n = plan[i]
+        spec = reqs[i]["spec"] if reqs[i]["spec"] is not None else hspec
+        hb = to_host(src)
+        exp = obuild(spec).pack(hb, 0, 1, 0, n)
+        assert first_diff(ref[int(offs[i]) + 3:int(offs[i]) + 3 + n], exp) is None, i
+    ms = mdt.Stream(torch.cuda.current_stream().cuda_stream)
+    out = zeros_dev(int(offs[-1]), 0)
+    b = mdt.Batch()
+    for (t, src, n), o in zip(plan, offs):
+        assert b.add_pack(src.data_ptr(), 1, t, 0, out.data_ptr() + int(o) + 3, n) == n
+    for policy in (0, 1):
+        for graph in (1, 0):
+            for tc in (256, 4096):
+                note(f"batch policy={policy} graph={graph} tile={tc}")
+                b.set_config(mdt.BatchConfig(tc, 4, policy, graph))
+                for rep in range(3):
+                    out.fill_(0)
+                    b.launch(ms)
+                    torch.cuda.synchronize()
+                    _ = (out[:1024].sum().item())  # eager work between replays
+                    assert first_diff(to_host(out), ref) is None, (policy, graph, tc, rep)
+    cfg = b.autotune(ms)
+    assert cfg.tile_chunks in (256, 512, 1024, 2048, 4096) and 1 <= cfg.wgs_per_cu <= 16
+    out.fill_(0)
+    b.launch(ms)
+    assert first_diff(to_host(out), ref) is None
+    assert total > 0
+    # change the descriptors: same batch object, new requests (unpack back)
+    b.clear()
+    back = {k: zeros_dev(v.numel(), 0) for k, v in arenas.items()}
+    exp_back = {k: np.zeros(v.numel(), np.uint8) for k, v in arenas.items()}
+    seen = set()
+    for i, ((t, src, n), o) in enumerate(zip(plan, offs)):
+        if reqs[i]["kind"] == "vector" or i % 3:
+            continue
+        spec = reqs[i]["spec"] if reqs[i]["spec"] is not None else hspec
+        key = reqs[i]["spec_key"]
+        if key in seen:
+            continue  # one request per type: faces of one array only meet where they carry equal bytes
+        seen.add(key)
+        b.add_unpack(out.data_ptr() + int(o) + 3, n, back[reqs[i]["kind"]].data_ptr(), 1, t, 0)
+        obuild(spec).unpack(ref[int(o) + 3:int(o) + 3 + n], exp_back[reqs[i]["kind"]], 0, 1)
+    note("batch after descriptor change")
+    for rep in range(2):
+        b.launch(ms)
+        torch.cuda.synchronize()
+    for k in back:
+        assert first_diff(to_host(back[k]), exp_back[k]) is None, k
+
+
+def test_server_mix_equals_alone(env):
+    torch, mdt = env
+    n_face, vec_count = 96, 1 << 13
+    reqs, hspec = _mix(400, 91, n_face, vec_count, hi=1 << 19)
+    arenas = {k: to_dev(inputs.random_bytes(_arena_bytes(k, n_face, vec_count), seed=60 + i))
+              for i, k in enumerate(("vector", "face", "hindexed"))}
+    cache = {}
+    for r in reqs:
+        if r["spec_key"] not in cache:
+            cache[r["spec_key"]] = mdt.build_type(r["spec"] if r["spec"] is not None else hspec)
+    srv = mdt.Server(nstreams=8, budget_bytes=1 << 30, max_batch=64, max_inflight=2)
+    srv.start()
+    note("server pack mix")
+    handles = []
+    for r in reqs:
+        t = cache[r["spec_key"]]
+        n = min(r["target"], t.size())
+        handles.append((srv.submit_pack(arenas[r["kind"]].data_ptr(), 1, t, 0, n), t, r, n))
+    outs = []
+    for h, t, r, n in handles:
+        srv.wait(h)
+        st, pk, nb, lat = srv.result(h)
+        assert st == 0 and nb == n and lat > 0
+        got = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+        if n:
+            torch.cuda.synchronize()
+            hip_copy(torch, got, pk, n)
+        alone = zeros_dev(n + 16, 0)
+        mdt.mdt_pack(arenas[r["kind"]].data_ptr(), 1, t, 0, alone.data_ptr(), n)
+        assert first_diff(to_host(got)[:n], to_host(alone)[:n]) is None
+        outs.append((h, t, r, n, got))
+    # unpack requests: scatter packed faces back through the server
+    note("server unpack mix")
+    seen = {}
+    ups = []
+    for h, t, r, n, got in outs:
+        if r["kind"] != "face" or r["spec_key"] in seen or n == 0:
+            continue
+        dst = zeros_dev(n_face ** 3 * 8, 0)
+        seen[r["spec_key"]] = dst
+        ups.append((srv.submit_unpack(got.data_ptr(), n, dst.data_ptr(), 1, t, 0), t, r, n, got, dst))
+    for h, t, r, n, got, dst in ups:
+        srv.wait(h)
+        assert srv.result(h)[0] == 0
+        exp = zeros_dev(n_face ** 3 * 8, 0)
+        mdt.mdt_unpack(got.data_ptr(), n, exp.data_ptr(), 1, t, 0)
+        assert torch.equal(dst, exp)
+        srv.release(h)
+    for h, *_ in outs:
+        srv.release(h)
+    s = srv.stats()
+    assert s["completed"] == len(handles) + len(ups) and s["failed"] == 0
+    assert s["p99_us"] >= s["p50_us"] > 0
+    srv.stop()
+    srv.close()
+
+
+def hip_copy(torch, dst_tensor, src_ptr, n):
+    """Device-to-device copy from a raw pointer (the server's arena)."""
+    import ctypes
+
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    rc = hip.hipMemcpy(ctypes.c_void_p(dst_tensor.data_ptr()), ctypes.c_void_p(src_ptr), n, 3)
+    assert rc == 0
+
+
+def test_server_budget_defers_and_failures_are_isolated(env):
+    torch, mdt = env
+    note("server budget / injected failures")
+    t = mdt.build_type(("vector", 1 << 16, 1, 2, inputs.DOUBLE))
+    src = to_dev(inputs.random_bytes(1 << 20, seed=71))
+    srv = mdt.Server(nstreams=2, budget_bytes=3 << 19, max_batch=4, max_inflight=1, arena_bytes=1 << 22)
+    srv.inject_alloc_failures(2)
+    hs = [srv.submit_pack(src.data_ptr(), 1, t, 0, -1) for _ in range(10)]
+    done = []
+    for h in hs:
+        srv.wait(h)
+        done.append(srv.result(h))
+        srv.release(h)  # frees its budget so queued requests can be admitted
+    codes = [d[0] for d in done]
+    assert codes[:2] == [mdt.ERR_NO_MEM, mdt.ERR_NO_MEM] and all(c == 0 for c in codes[2:])
+    s = srv.stats()
+    assert s["failed"] == 2 and s["completed"] == 8
+    assert s["deferred"] > 0 and s["peak_inflight_bytes"] <= 3 << 19
+    # shutdown drains requests still queued
+    more = [srv.submit_pack(src.data_ptr(), 1, t, 0, -1) for _ in range(5)]
+    srv.close()
+    assert all(h for h in more)

@@ -1,0 +1,211 @@
+"""GPU parity: every byte the gfx950 kernels move must equal the oracle's.
+
+Pack, partial pack, unpack (into canary-filled buffers, so gaps are proven
+untouched) and the device flatten are compared element by element with the
+oracle on the same seeded inputs: random tiny types of every constructor at
+odd buffer alignments, the small vector case, and mid-size versions of the
+halo-face, hindexed and particle-record layouts that span many tiles and
+end in a ragged tail.  Full-size workloads are in test_gpu_fullsize.py.
+"""
+import numpy as np
+import pytest
+
+import bruteforce as bf
+from gpu_util import first_diff, note, to_dev, to_host, zeros_dev
+from oracle import build_type as obuild
+from paper_2402_12274_amd import inputs
+from typegen import buffer_for, tiny_specs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mdt():
+    from gpu_util import torch_cuda
+
+    torch_cuda()
+    from paper_2402_12274_amd import mdt as m
+
+    return m
+
+
+def _pack_dev(mdt, t, src_dev, origin, count, off, mx, out_shift=0):
+    total = count * t.size()
+    n = max(0, total - off)
+    if mx >= 0:
+        n = min(n, mx)
+    out = zeros_dev(n + 32, 0xEE)
+    got = mdt.mdt_pack(src_dev.data_ptr() + origin, count, t, off, out.data_ptr() + out_shift, mx)
+    assert got == n
+    h = to_host(out)
+    assert (h[:out_shift] == 0xEE).all() and (h[out_shift + n:] == 0xEE).all(), "pack wrote outside its output"
+    return h[out_shift:out_shift + n]
+
+
+SPECS = tiny_specs(99, 120)
+
+
+@pytest.mark.parametrize("i", range(len(SPECS)))
+def test_random_types_pack_unpack(mdt, i):
+    spec = SPECS[i]
+    note(f"random type {i}: {spec}")
+    tm = bf.typemap(spec)
+    t = mdt.build_type(spec)
+    o = obuild(spec)
+    for count in (1, 3):
+        size, origin = buffer_for(tm, count, pad=64)
+        host = inputs.random_bytes(size, seed=1000 + i)
+        src = to_dev(host)
+        total = count * tm.size
+        full = o.pack(host, origin, count)
+        for shift in (0, 3, 8):
+            got = _pack_dev(mdt, t, src, origin, count, 0, -1, shift)
+            assert first_diff(got, full) is None, (spec, count, shift, first_diff(got, full))
+        for off, mx in [(1, 5), (total // 2, 17), (3, total), (total, 4), (total + 2, -1), (0, 0)]:
+            got = _pack_dev(mdt, t, src, origin, count, off, mx, 5)
+            exp = o.pack(host, origin, count, off, mx)
+            assert first_diff(got, exp) is None, (spec, count, off, mx)
+        if bf.overlaps(tm, count):
+            dst = zeros_dev(size, 0x5A)
+            with pytest.raises(mdt.MdtError) as e:
+                mdt.mdt_unpack(to_dev(full).data_ptr(), total, dst.data_ptr() + origin, count, t, 0)
+            assert e.value.code == mdt.ERR_OVERLAP
+            continue
+        for off, n in [(0, total), (total // 3, total - total // 3), (1, max(0, min(7, total - 1)))]:
+            canary = np.full(size, 0x5A, np.uint8)
+            exp = canary.copy()
+            if n > 0:
+                o.unpack(full[off:off + n], exp, origin, count, off)
+            dst = to_dev(canary)
+            packed = zeros_dev(n + 16, 0)
+            packed[3:3 + n] = to_dev(full[off:off + n]) if n > 0 else packed[3:3]
+            got = mdt.mdt_unpack(packed.data_ptr() + 3, n, dst.data_ptr() + origin, count, t, off)
+            assert got == n
+            h = to_host(dst)
+            assert first_diff(h, exp) is None, (spec, count, off, n, first_diff(h, exp))
+
+
+def test_small_vector_case(mdt):
+    note("small vector case")
+    spec = inputs.vector_small()
+    t = mdt.build_type(spec)
+    o = obuild(spec)
+    assert t.iov_len(-1) == o.iov_len(-1) == (1024, 8192)
+    assert t.iov_len(4096) == o.iov_len(4096) == (512, 4096)
+    b, ln = t.iov(512, 4)
+    ob, ol = o.iov(512, 4)
+    assert np.array_equal(b, ob) and np.array_equal(ln, ol) and b[0] == 8192
+    host = inputs.random_bytes(16384, seed=inputs.DEFAULT_SEED)
+    src = to_dev(host)
+    packed = _pack_dev(mdt, t, src, 0, 1, 0, -1)
+    assert first_diff(packed, o.pack(host, 0, 1)) is None
+    dst = zeros_dev(16384, 0)
+    mdt.mdt_unpack(to_dev(packed).data_ptr(), 8192, dst.data_ptr(), 1, t, 0)
+    h = to_host(dst)
+    exp = np.zeros(16384, np.uint8)
+    o.unpack(packed, exp, 0, 1)
+    assert first_diff(h, exp) is None
+    # round trip: covered bytes restored, the gaps stay zero
+    view = host.reshape(1024, 16)
+    assert np.array_equal(h.reshape(1024, 16)[:, :8], view[:, :8]) and not h.reshape(1024, 16)[:, 8:].any()
+
+
+def _layout_case(mdt, spec, count, src_bytes, origin, seed, chunk):
+    t = mdt.build_type(spec)
+    o = obuild(spec)
+    host = inputs.random_bytes(src_bytes, seed=seed)
+    src = to_dev(host)
+    full = o.pack(host, origin, count)
+    got = _pack_dev(mdt, t, src, origin, count, 0, -1)
+    assert first_diff(got, full) is None, first_diff(got, full)
+    # partial packs with a byte budget concatenate to the full stream
+    parts = []
+    off = 0
+    while off < full.size:
+        parts.append(_pack_dev(mdt, t, src, origin, count, off, chunk, off % 13))
+        off += chunk
+    assert first_diff(np.concatenate(parts), full) is None
+    # unpack into a canary buffer, chunk by chunk
+    canary = np.full(src_bytes, 0x77, np.uint8)
+    exp = canary.copy()
+    o.unpack(full, exp, origin, count)
+    dst = to_dev(canary)
+    pk = to_dev(full)
+    off = 0
+    while off < full.size:
+        n = min(chunk, full.size - off)
+        mdt.mdt_unpack(pk.data_ptr() + off, n, dst.data_ptr() + origin, count, t, off)
+        off += n
+    h = to_host(dst)
+    assert first_diff(h, exp) is None, first_diff(h, exp)
+
+
+def test_halo_faces_midsize(mdt):
+    n = 96
+    for label, spec in inputs.halo_faces(n):
+        note(f"halo face {label} n={n}")
+        _layout_case(mdt, spec, 1, n ** 3 * 8, 0, seed=hash(label) & 0xffff, chunk=(1 << 14) + 9)
+
+
+def test_hindexed_midsize(mdt):
+    lens, disps = inputs.hindexed_blocks(nblocks=20000, span=1 << 22, seed=3)
+    note("hindexed midsize")
+    _layout_case(mdt, inputs.hindexed_type(lens, disps), 1, 1 << 22, 0, seed=4, chunk=(1 << 16) + 3)
+    lens, disps = inputs.hindexed_blocks(nblocks=20000, span=1 << 22, seed=5, permute=False)
+    _layout_case(mdt, inputs.hindexed_type(lens, disps), 2, 1 << 23, 0, seed=6, chunk=1 << 16)
+
+
+def test_particle_records_midsize(mdt):
+    note("particle records midsize")
+    count = 50001
+    _layout_case(mdt, inputs.particle_struct(), count, count * 40, 0, seed=8, chunk=(1 << 16) - 1)
+
+
+def test_contiguous_and_degenerate(mdt):
+    note("contiguous / degenerate")
+    host = inputs.random_bytes(1 << 20, seed=9)
+    src = to_dev(host)
+    t = mdt.build_type(("contiguous", 1 << 17, inputs.DOUBLE))
+    for off, mx, shift in [(0, -1, 0), (5, 99999, 7), (1 << 19, 1 << 18, 1)]:
+        got = _pack_dev(mdt, t, src, 0, 1, off, mx, shift)
+        exp = host[off:off + (len(host) - off if mx < 0 else mx)]
+        assert first_diff(got, exp) is None
+    # count 0, offset past the end, zero budget: no bytes, no writes
+    for cnt, off, mx in [(0, 0, -1), (1, 1 << 20, -1), (1, 100, 0)]:
+        assert _pack_dev(mdt, t, src, 0, cnt, off, mx).size == 0
+    # an empty type
+    e = mdt.build_type(("vector", 0, 1, 2, inputs.DOUBLE))
+    assert _pack_dev(mdt, e, src, 0, 5, 0, -1).size == 0
+    # truncation is an error and writes nothing
+    dst = zeros_dev(64, 0)
+    with pytest.raises(mdt.MdtError) as ex:
+        mdt.mdt_unpack(src.data_ptr(), 65, dst.data_ptr(), 1, mdt.build_type(("contiguous", 8, inputs.DOUBLE)), 0)
+    assert ex.value.code == mdt.ERR_TRUNCATE
+    assert not to_host(dst).any()
+
+
+def test_device_flatten_matches_oracle(mdt):
+    import ctypes
+
+    torch = pytest.importorskip("torch")
+    specs = [inputs.vector_small(), inputs.particle_struct(), inputs.halo_face(64, 1, 2, "lo"),
+             inputs.halo_face(64, 4, 1, "hi"), ("contiguous", 4, ("vector", 3, 1, 2, inputs.DOUBLE))]
+    lens, disps = inputs.hindexed_blocks(nblocks=5000, span=1 << 20, seed=11)
+    specs.append(inputs.hindexed_type(lens, disps))
+    specs += tiny_specs(5, 30)
+    s = mdt.Stream(0)
+    for spec in specs:
+        note(f"flatten {str(spec)[:80]}")
+        t = mdt.build_type(spec)
+        o = obuild(spec)
+        nseg = o.iov_len(-1)[0]
+        for off, m in [(0, nseg), (nseg // 3, 1000), (nseg, 5)]:
+            out = torch.zeros(max(1, min(m, max(0, nseg - off))) * 2, dtype=torch.int64, device="cuda")
+            base = 1 << 40
+            got, _ = mdt.mdt_type_iov_enqueue(t, off, out.data_ptr(), m, base, s)
+            torch.cuda.synchronize()
+            ob, ol = o.iov(off, m)
+            assert got == ob.size
+            h = out.cpu().numpy()[: 2 * got].reshape(-1, 2)
+            assert np.array_equal(h[:, 0] - base, ob) and np.array_equal(h[:, 1], ol), spec
+    assert ctypes.sizeof(mdt.Iov) == 16
