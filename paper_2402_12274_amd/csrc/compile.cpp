@@ -723,12 +723,88 @@ void lower(TypeNode *t, const Layout &L, Compiled &C)
     C.self_disjoint = compute_self_disjoint(L);
 }
 
+// Record view of a single-group layout: records are the count elements
+// (shape without loops) or the iterations of the shape's only loop.
+void lower_records(const Layout &L, Compiled &C)
+{
+    DevLayout &D = C.host;
+    DevRecords &R = D.rec;
+    std::memset(&R, 0, sizeof R);
+    if (D.kind != KIND_SINGLE) return;
+    const Shape &S = L.shapes[0];
+    int64_t X, U = leaf_bytes(S);
+    bool count1 = false;
+    if (S.loops.empty()) {
+        X = D.extent;
+    } else if (S.loops.size() == 1) {
+        X = S.loops[0].stride;
+        count1 = D.extent != S.loops[0].cnt * S.loops[0].stride;
+    } else {
+        return;
+    }
+    if (X <= 0 || X > REC_MAX_X || U < 1 || U > REC_MAX_U || X > 4 * U) return;
+    int64_t lo = INT64_MAX, hi = INT64_MIN;
+    for (const Run &r : S.leaf) {
+        lo = std::min(lo, r.off);
+        hi = std::max(hi, r.off + r.len);
+    }
+    if (hi - lo > 65535) return;
+    // LDS for a tile: typed span (+ slack) + packed tile, and both tables
+    int tc = 512;
+    auto need = [&](int c) {
+        int64_t nrec = (16 * (int64_t)c + U - 1) / U + 1;
+        int64_t span = (nrec - 1) * X + (hi - lo) + 48;
+        int64_t pk = 16 * (int64_t)c + 48;
+        return ((std::max(span, pk) + 15) & ~(int64_t)15) + 4 * std::max<int64_t>(U, X) + 16;
+    };
+    while (tc > 64 && need(tc) > 40 * 1024) tc /= 2;
+    if (need(tc) > 40 * 1024) return;
+    C.rec_ptab.assign((size_t)U, 0);
+    int64_t q = 0;
+    for (const Run &r : S.leaf)
+        for (int64_t i = 0; i < r.len; i++, q++)
+            C.rec_ptab[q] = (uint32_t)(r.off + i - lo) | (uint32_t)(r.len - i) << 16;
+    // typed -> packed table (unpack), when records do not interleave and no
+    // byte of a record is covered twice
+    bool ok = hi - lo <= X;
+    if (ok) {
+        C.rec_ttab.assign((size_t)X, 0);
+        q = 0;
+        for (const Run &r : S.leaf) {
+            for (int64_t i = 0; i < r.len; i++) {
+                uint32_t &e = C.rec_ttab[r.off + i - lo];
+                if (e & 0x80000000u) ok = false;
+                e = 0x80000000u | (uint32_t)(q + i) | (uint32_t)std::min<int64_t>(r.len - i, 0x7fff) << 16;
+            }
+            q += r.len;
+        }
+    }
+    if (!ok) C.rec_ttab.clear();
+    R.on = 1;
+    R.U = (int32_t)U;
+    R.X = (int32_t)X;
+    R.lo = (int32_t)lo;
+    R.hi = (int32_t)hi;
+    R.unpack_ok = ok;
+    R.B0 = L.groups[0].disp;
+    R.dU = make_magic((uint64_t)U);
+    R.dU32 = make_magic32((uint32_t)U);
+    R.dX32 = make_magic32((uint32_t)X);
+    R.tile_chunks = tc;
+    R.lds_bytes = (int32_t)need(tc);
+    R.ptab = C.rec_ptab.data();
+    R.ttab = ok ? C.rec_ttab.data() : nullptr;
+    C.rec_count1_only = count1;
+    R.count1_only = count1;
+}
+
 std::shared_ptr<Compiled> make_compiled(TypeNode *t)
 {
     LayoutP L0 = compile_node(t);
     auto C = std::make_shared<Compiled>();
     C->layout = std::make_shared<Layout>(finalize(L0));
     lower(t, *C->layout, *C);
+    lower_records(*C->layout, *C);
     return C;
 }
 

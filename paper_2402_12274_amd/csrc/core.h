@@ -84,6 +84,8 @@ struct Compiled {
     std::vector<int32_t> gshape, gdir;
     std::vector<DevShape> shapes;
     std::vector<std::vector<int64_t>> leaf_store;  // big leaf arrays (off, len, pre per shape)
+    std::vector<uint32_t> rec_ptab, rec_ttab;       // record-view byte tables
+    bool rec_count1_only = false;                   // record view holds for element 0 only
     int64_t nruns = 0;
     bool merge_free = true;
     // segment table for layouts that are not merge-free, built on demand

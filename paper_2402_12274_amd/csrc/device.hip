@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -91,6 +92,8 @@ int device_tables(Compiled *c, DeviceTables **out)
     size_t off_grpre = off; off += al256(c->grpre.size() * sizeof(int64_t));
     size_t off_gshape = off; off += al256(c->gshape.size() * sizeof(int32_t));
     size_t off_gdir = off; off += al256(c->gdir.size() * sizeof(int32_t));
+    size_t off_ptab = off; off += al256(c->rec_ptab.size() * sizeof(uint32_t));
+    size_t off_ttab = off; off += al256(c->rec_ttab.size() * sizeof(uint32_t));
     size_t off_lay = off; off += al256(sizeof(DevLayout));
     std::vector<uint8_t> blob(off, 0);
     uint8_t *base = nullptr;
@@ -123,6 +126,8 @@ int device_tables(Compiled *c, DeviceTables **out)
     put(off_grpre, c->grpre.data(), c->grpre.size() * 8);
     put(off_gshape, c->gshape.data(), c->gshape.size() * 4);
     put(off_gdir, c->gdir.data(), c->gdir.size() * 4);
+    put(off_ptab, c->rec_ptab.data(), c->rec_ptab.size() * 4);
+    put(off_ttab, c->rec_ttab.data(), c->rec_ttab.size() * 4);
     DevLayout &L = d->lay;
     if (nsh) L.shape0 = shapes[0];
     L.shapes = nsh ? (const DevShape *)(base + off_shapes) : nullptr;
@@ -131,6 +136,8 @@ int device_tables(Compiled *c, DeviceTables **out)
     L.grpre = H.grpre ? (const int64_t *)(base + off_grpre) : nullptr;
     L.gshape = H.gshape ? (const int32_t *)(base + off_gshape) : nullptr;
     L.gdir = H.gdir ? (const int32_t *)(base + off_gdir) : nullptr;
+    L.rec.ptab = H.rec.ptab ? (const uint32_t *)(base + off_ptab) : nullptr;
+    L.rec.ttab = H.rec.ttab ? (const uint32_t *)(base + off_ttab) : nullptr;
     std::memcpy(blob.data() + off_lay, &L, sizeof(DevLayout));
     d->d_lay = (DevLayout *)(base + off_lay);
     e = hipMemcpy(base, blob.data(), off, hipMemcpyHostToDevice);
@@ -154,6 +161,17 @@ __global__ __launch_bounds__(256) void xfer_kernel(const DevLayout L, const Xfer
         if (UNPACK) unpack_chunk<KIND>(L, A, c);
         else pack_chunk<KIND>(L, A, c);
     }
+}
+
+// dense record streams: one tile of chunks per workgroup, staged in LDS
+template <bool UNPACK>
+__global__ __launch_bounds__(256) void dense_kernel(const DevLayout L, const XferArgs A)
+{
+    extern __shared__ __align__(16) uint8_t lds_dyn[];
+    int64_t c0 = xcd_tile() * A.tile_chunks;
+    int64_t c1 = c0 + A.tile_chunks < A.nchunks ? c0 + A.tile_chunks : A.nchunks;
+    if (UNPACK) dense_unpack_tile(L, A, c0, c1, lds_dyn);
+    else dense_pack_tile(L, A, c0, c1, lds_dyn);
 }
 
 // flatten: one lane per segment
@@ -186,10 +204,37 @@ int64_t default_tile_chunks(int64_t nchunks)
     return nchunks >= ((int64_t)1 << 19) ? 1024 : 256;
 }
 
+static bool dense_enabled()
+{
+    static const bool on = [] {
+        const char *e = getenv("MDT_DENSE");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
+bool use_dense(const DevLayout &L, const XferArgs &A, bool unpack)
+{
+    const DevRecords &R = L.rec;
+    if (!R.on || !dense_enabled()) return false;
+    if (R.count1_only && A.off + A.nbytes > L.size) return false;
+    return !unpack || R.unpack_ok;
+}
+
 int launch_xfer(const DevLayout &L, const XferArgs &A0, bool unpack, hipStream_t s)
 {
     if (A0.nbytes == 0 || L.kind == KIND_EMPTY) return MDT_SUCCESS;
     XferArgs A = A0;
+    if (use_dense(L, A, unpack)) {
+        A.tile_chunks = L.rec.tile_chunks;
+        int64_t grid = (A.nchunks + A.tile_chunks - 1) / A.tile_chunks;
+        if (grid > 0x7fffffff) return MDT_ERR_ARG;
+        size_t lds = (size_t)L.rec.lds_bytes;
+        if (unpack) hipLaunchKernelGGL(dense_kernel<true>, dim3((unsigned)grid), dim3(256), lds, s, L, A);
+        else hipLaunchKernelGGL(dense_kernel<false>, dim3((unsigned)grid), dim3(256), lds, s, L, A);
+        HIPCHK(hipGetLastError());
+        return MDT_SUCCESS;
+    }
     if (A.tile_chunks <= 0) A.tile_chunks = default_tile_chunks(A.nchunks);
     int64_t grid = (A.nchunks + A.tile_chunks - 1) / A.tile_chunks;
     if (grid > 0x7fffffff) return MDT_ERR_ARG;

@@ -93,6 +93,63 @@ struct DevShape {
     const int64_t *lpre_p;
 };
 
+// n / d for 0 <= n < 2^31 and 1 <= d < 2^31 with a 32-bit high multiply:
+// m = ceil(2^(31+l) / d) < 2^32, q = mulhi(n, m) >> (l-1), l = ceil(log2 d).
+struct MagicDiv32 {
+    uint32_t m;
+    uint32_t s;
+    uint32_t one;
+};
+
+MDT_HD uint32_t magic_div32(uint32_t n, const MagicDiv32 &d)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return d.one ? n : (__umulhi(n, d.m) >> d.s);
+#else
+    return d.one ? n : (uint32_t)(((uint64_t)n * d.m) >> 32) >> d.s;
+#endif
+}
+
+inline MagicDiv32 make_magic32(uint32_t d)
+{
+    MagicDiv32 r{0, 0, 0};
+    if (d <= 1) {
+        r.one = 1;
+        return r;
+    }
+    uint32_t l = 0;
+    while (l < 32 && ((uint64_t)1 << l) < d) l++;
+    uint64_t num = (uint64_t)1 << (31 + l);
+    r.m = (uint32_t)((num + d - 1) / d);
+    r.s = l - 1;
+    return r;
+}
+
+// Record view: the packed stream is a sequence of equally spaced records
+// (element e at byte B0 + e*X), each holding the same leaf runs, U packed
+// bytes in total.  Dense record streams (small X/U) are moved by staging a
+// tile's typed span in LDS and mapping bytes through per-record tables.
+constexpr int32_t REC_MAX_U = 4096;
+constexpr int32_t REC_MAX_X = 4096;
+
+struct DevRecords {
+    int32_t on;        // 1 when the view applies
+    int32_t U;         // packed bytes per record
+    int32_t X;         // byte stride of records (> 0)
+    int32_t lo, hi;    // a record's bytes lie in [origin + lo, origin + hi)
+    int32_t unpack_ok; // hi - lo <= X and no byte of a record is covered twice
+    int32_t count1_only; // the view describes element 0 of a count only
+    int32_t pad_;
+    int64_t B0;        // displacement of record 0's origin
+    MagicDiv dU;       // 64-bit divisions by U
+    MagicDiv32 dU32;   // 32-bit divisions by U and X
+    MagicDiv32 dX32;
+    int32_t tile_chunks; // chunks per tile for which the spans fit in LDS
+    int32_t lds_bytes;   // dynamic LDS for that tile (spans + table)
+    const uint32_t *ptab;  // [U] packed q -> (typed offset - lo) | (run bytes left from q) << 16
+    const uint32_t *ttab;  // [X] typed offset d - lo -> q | (run bytes left) << 16 | valid << 31
+};
+
 enum LayoutKind : int32_t {
     KIND_EMPTY = 0,   // no bytes
     KIND_CONTIG = 1,  // the packed stream is one contiguous run: addr = base + p
@@ -127,6 +184,7 @@ struct DevLayout {
     const int32_t *gdir;    // [ndir] group containing byte k << dir_shift of the group list
     const DevShape *shapes; // [nshapes]
     DevShape shape0;        // copy of shapes[0]
+    DevRecords rec;         // record view (rec.on == 0 when it does not apply)
 };
 
 // Result of locating a packed-stream byte position.

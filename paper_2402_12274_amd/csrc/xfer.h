@@ -195,3 +195,156 @@ __device__ __forceinline__ int64_t xcd_tile()
 }
 
 }  // namespace mdt
+
+namespace mdt {
+
+// ---------------------------------------------------------------------------
+// dense record streams: stage the tile's typed span (pack) or packed bytes
+// (unpack) in LDS with coalesced 16-byte loads, then move every byte through
+// the per-record tables with 32-bit arithmetic.  The packed side is stored
+// as whole 16-byte chunks (pack) and the typed side as naturally aligned
+// dwords covering only typemap bytes (unpack: gaps are never written).
+
+// 4 bytes from byte offset `off` of an LDS buffer (two aligned reads; the
+// buffer has a dword of slack at its end)
+__device__ __forceinline__ uint32_t lds_u32(const uint8_t *lds, uint32_t off)
+{
+    const uint32_t *p = (const uint32_t *)(lds + (off & ~3u));
+    return __builtin_amdgcn_alignbyte(p[1], p[0], off & 3u);
+}
+
+__device__ __forceinline__ uint32_t lds_u8(const uint8_t *lds, uint32_t off) { return lds[off]; }
+
+// Copy [g_lo, g_hi) rounded out to 16-byte blocks into LDS; returns the LDS
+// offset of g_lo.  Every block read holds at least one byte of the range.
+__device__ __forceinline__ uint32_t stage_span(uint8_t *lds, const uint8_t *g_lo, const uint8_t *g_hi)
+{
+    uintptr_t a = (uintptr_t)g_lo & ~(uintptr_t)15;
+    uintptr_t b = ((uintptr_t)g_hi + 15) & ~(uintptr_t)15;
+    uint32_t nv = (uint32_t)((b - a) >> 4);
+    for (uint32_t i = threadIdx.x; i < nv; i += blockDim.x) {
+        u32x4 v = __builtin_nontemporal_load((const u32x4 *)(a + 16 * (uintptr_t)i));
+        *(u32x4 *)(lds + 16 * i) = v;
+    }
+    return (uint32_t)((uintptr_t)g_lo - a);
+}
+
+// Pack chunks [c0, c1) of A (a tile) with the record view of L.  `lds`
+// holds rec.lds_bytes of dynamic shared memory.
+__device__ __forceinline__ void dense_pack_tile(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t c1,
+                                                uint8_t *lds)
+{
+    const DevRecords &R = L.rec;
+    const int64_t P_lo = max(16 * c0 - A.head, (int64_t)0);
+    const int64_t P_hi = min(16 * c1 - A.head, A.nbytes);
+    const uint64_t s_lo = (uint64_t)(A.off + P_lo);
+    const uint64_t e0 = magic_div(s_lo, R.dU);
+    const uint64_t e1 = magic_div((uint64_t)(A.off + P_hi - 1), R.dU);
+    const int64_t t_lo = R.B0 + (int64_t)e0 * R.X + R.lo;
+    const int64_t t_hi = R.B0 + (int64_t)e1 * R.X + R.hi;
+    uint32_t *tab = (uint32_t *)lds;
+    uint8_t *span = lds + ((4 * (uint32_t)R.U + 15) & ~15u);
+    for (int q = threadIdx.x; q < R.U; q += blockDim.x) tab[q] = R.ptab[q];
+    const uint32_t base = stage_span(span, A.typed + t_lo, A.typed + t_hi);
+    __syncthreads();
+    const uint32_t q0 = (uint32_t)(s_lo - e0 * (uint64_t)R.U);  // position of s_lo in record e0
+    const uint32_t U = (uint32_t)R.U, X = (uint32_t)R.X;
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+        const int64_t lo = 16 * c - A.head;
+        const int64_t a = lo > 0 ? lo : 0;
+        const int64_t b = lo + 16 < A.nbytes ? lo + 16 : A.nbytes;
+        // record and offset of chunk byte a, relative to record e0
+        uint32_t rel = (uint32_t)(a - P_lo) + q0;
+        uint32_t er = magic_div32(rel, R.dU32);
+        uint32_t q = rel - er * U;
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+        if (a == lo && b == lo + 16) {
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                uint32_t e = tab[q];
+                if ((e >> 16) >= 4u) {
+                    w[t] = lds_u32(span, base + er * X + (e & 0xffffu));
+                    q += 4;
+                    if (q == U) { q = 0; er++; }
+                } else {
+                    uint32_t v = 0;
+#pragma unroll
+                    for (int i = 0; i < 4; i++) {
+                        uint32_t ei = tab[q];
+                        v |= lds_u8(span, base + er * X + (ei & 0xffffu)) << (8 * i);
+                        if (++q == U) { q = 0; er++; }
+                    }
+                    w[t] = v;
+                }
+            }
+            u32x4 v = {w[0], w[1], w[2], w[3]};
+            __builtin_nontemporal_store(v, (u32x4 *)(A.packed - A.head + 16 * c));
+        } else {
+            uint8_t *dst = A.packed - A.head + 16 * c;
+            for (int i = (int)(a - lo); i < (int)(b - lo); i++) {
+                uint32_t ei = tab[q];
+                dst[i] = (uint8_t)lds_u8(span, base + er * X + (ei & 0xffffu));
+                if (++q == U) { q = 0; er++; }
+            }
+        }
+    }
+}
+
+// Unpack chunks [c0, c1) of A (a tile): the packed tile goes to LDS, then the
+// lanes walk the typed span dword by dword and store the typemap bytes that
+// belong to this tile.
+__device__ __forceinline__ void dense_unpack_tile(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t c1,
+                                                  uint8_t *lds)
+{
+    const DevRecords &R = L.rec;
+    const int64_t P_lo = max(16 * c0 - A.head, (int64_t)0);
+    const int64_t P_hi = min(16 * c1 - A.head, A.nbytes);
+    const uint64_t s_lo = (uint64_t)(A.off + P_lo);
+    const uint64_t e0 = magic_div(s_lo, R.dU);
+    const uint64_t e1 = magic_div((uint64_t)(A.off + P_hi - 1), R.dU);
+    const int64_t t_lo = R.B0 + (int64_t)e0 * R.X + R.lo;
+    const int64_t t_hi = R.B0 + (int64_t)e1 * R.X + R.hi;
+    uint32_t *tab = (uint32_t *)lds;
+    uint8_t *pk = lds + ((4 * (uint32_t)R.X + 15) & ~15u);
+    for (int d = threadIdx.x; d < R.X; d += blockDim.x) tab[d] = R.ttab[d];
+    const uint32_t pbase = stage_span(pk, A.packed + P_lo, A.packed + P_hi);
+    __syncthreads();
+    const uint32_t U = (uint32_t)R.U, X = (uint32_t)R.X;
+    const uint32_t q0 = (uint32_t)(s_lo - e0 * (uint64_t)U);  // packed position of s_lo in record e0
+    const uint32_t npk = (uint32_t)(P_hi - P_lo);             // packed bytes of this tile
+    uint8_t *t0 = const_cast<uint8_t *>(A.typed) + t_lo;      // typed byte of (record e0, offset lo)
+    const uintptr_t d_lo = (uintptr_t)t0 & ~(uintptr_t)3;
+    const uint32_t skew = (uint32_t)((uintptr_t)t0 - d_lo);   // bytes of the first dword before t0
+    const uint32_t tspan = (uint32_t)(t_hi - t_lo);
+    const uint32_t ndw = (skew + tspan + 3) >> 2;
+    for (uint32_t j = threadIdx.x; j < ndw; j += blockDim.x) {
+        uint32_t *D = (uint32_t *)(d_lo + 4 * (uintptr_t)j);
+        int32_t r0 = (int32_t)(4 * j) - (int32_t)skew;  // typed offset of the dword from t0
+        if (r0 >= 0 && (uint32_t)r0 + 4 <= tspan) {
+            uint32_t er = magic_div32((uint32_t)r0, R.dX32);
+            uint32_t d = (uint32_t)r0 - er * X;
+            uint32_t e = tab[d];
+            // packed offset in this tile = er*U + q - q0
+            int32_t p = (int32_t)(er * U + (e & 0xffffu)) - (int32_t)q0;
+            if ((e & 0x80000000u) && ((e >> 16) & 0x7fffu) >= 4u && p >= 0 && (uint32_t)p + 4 <= npk) {
+                *D = lds_u32(pk, pbase + (uint32_t)p);
+                continue;
+            }
+        }
+        // partial dword: byte by byte
+        uint8_t *Db = (uint8_t *)D;
+        for (int i = 0; i < 4; i++) {
+            int32_t r = r0 + i;
+            if (r < 0 || (uint32_t)r >= tspan) continue;
+            uint32_t er = magic_div32((uint32_t)r, R.dX32);
+            uint32_t d = (uint32_t)r - er * X;
+            uint32_t e = tab[d];
+            if (!(e & 0x80000000u)) continue;
+            int32_t p = (int32_t)(er * U + (e & 0xffffu)) - (int32_t)q0;
+            if (p < 0 || (uint32_t)p >= npk) continue;
+            Db[i] = (uint8_t)lds_u8(pk, pbase + (uint32_t)p);
+        }
+    }
+}
+
+}  // namespace mdt
