@@ -111,6 +111,26 @@ def cpu_baseline(W, budget_s):
                        f"nproc={os.cpu_count()})")
 
 
+def copy_ceiling_gbs(torch, dev, nbytes=1 << 30, reps=10):
+    """Measured device-to-device copy rate (read + write bytes) of 1 GiB."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    a.fill_(1)
+    b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(reps):
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    times.sort()
+    del a, b
+    return round(2 * nbytes / times[len(times) // 2] / 1e9, 1)
+
+
 # ---------------------------------------------------------------------------
 
 
@@ -202,6 +222,7 @@ def main():
     dt = time.perf_counter() - t0
 
     value = step_bytes * args.steps / dt / 1e9
+    copy_ceiling = copy_ceiling_gbs(torch, dev)
     # dominant direction: the one with the larger total kernel time
     per = {}
     for k, lst in ev_log.items():
@@ -228,7 +249,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": W["desc"], "mode": args.mode, "requests_per_step": 2 * len(types),
                    "packed_bytes_per_step": sum(sizes), "rotating_copies": R,
-                   "frac_of_peak_value": round(value / PEAK_HBM_GBS, 4)},
+                   "frac_of_peak_value": round(value / PEAK_HBM_GBS, 4),
+                   "device_copy_ceiling_GBps": copy_ceiling},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
                      "kernel": f"{dom} ({'batched launch' if batches else 'one launch per request'})",

@@ -34,6 +34,7 @@ struct ReqDesc {
     uint8_t *packed;
     int64_t off, nbytes, head, nchunks;
     int32_t unpack, kind;
+    int32_t elem1, dense;
 };
 
 struct BatchHeader {
@@ -57,6 +58,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restric
                                                     unsigned long long *counter)
 {
     __shared__ __align__(16) uint32_t s_lay[LAY_WORDS];
+    extern __shared__ __align__(16) uint8_t lds_dyn[];
     __shared__ int64_t s_t;
     const int64_t ntiles = H->ntiles, T = H->tile_chunks, nreq = H->nreq;
     int64_t cur = -1;
@@ -93,22 +95,31 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restric
         A.head = D.head;
         A.nchunks = D.nchunks;
         A.tile_chunks = T;
+        A.elem1 = D.elem1;
         int64_t c0 = (t - tile0[lo]) * T;
         int64_t cend = c0 + T < D.nchunks ? c0 + T : D.nchunks;
-        if (D.unpack) {
-            if (D.kind == KIND_CONTIG)
-                for (int64_t c = c0 + threadIdx.x; c < cend; c += 256) unpack_chunk<KIND_CONTIG>(L, A, c);
-            else if (D.kind == KIND_SINGLE)
-                for (int64_t c = c0 + threadIdx.x; c < cend; c += 256) unpack_chunk<KIND_SINGLE>(L, A, c);
-            else
-                for (int64_t c = c0 + threadIdx.x; c < cend; c += 256) unpack_chunk<KIND_MULTI>(L, A, c);
+        if (D.dense) {
+            // sub-tiles sized to the type's LDS budget; LDS is reused between them
+            const int64_t st = L.rec.tile_chunks;
+            for (int64_t s0 = c0; s0 < cend; s0 += st) {
+                int64_t s1 = s0 + st < cend ? s0 + st : cend;
+                if (D.unpack) dense_unpack_tile(L, A, s0, s1, lds_dyn);
+                else dense_pack_tile(L, A, s0, s1, lds_dyn);
+                __syncthreads();
+            }
         } else {
-            if (D.kind == KIND_CONTIG)
-                for (int64_t c = c0 + threadIdx.x; c < cend; c += 256) pack_chunk<KIND_CONTIG>(L, A, c);
-            else if (D.kind == KIND_SINGLE)
-                for (int64_t c = c0 + threadIdx.x; c < cend; c += 256) pack_chunk<KIND_SINGLE>(L, A, c);
-            else
-                for (int64_t c = c0 + threadIdx.x; c < cend; c += 256) pack_chunk<KIND_MULTI>(L, A, c);
+            for (int64_t s0 = c0; s0 < cend; s0 += 1024) {
+                int64_t s1 = s0 + 1024 < cend ? s0 + 1024 : cend;
+                if (D.unpack) {
+                    if (D.kind == KIND_CONTIG) unpack_tile4<KIND_CONTIG>(L, A, s0, s1);
+                    else if (D.kind == KIND_SINGLE) unpack_tile4<KIND_SINGLE>(L, A, s0, s1);
+                    else unpack_tile4<KIND_MULTI>(L, A, s0, s1);
+                } else {
+                    if (D.kind == KIND_CONTIG) pack_tile4<KIND_CONTIG>(L, A, s0, s1);
+                    else if (D.kind == KIND_SINGLE) pack_tile4<KIND_SINGLE>(L, A, s0, s1);
+                    else pack_tile4<KIND_MULTI>(L, A, s0, s1);
+                }
+            }
         }
         if (POLICY == 0) {
             t += gridDim.x;
@@ -130,6 +141,7 @@ constexpr uint32_t BATCH_MAGIC = 0x6d647442u;
 struct BatchReq {
     TypeNode *type;  // retained
     ReqDesc d;
+    int32_t lds;     // dynamic LDS the request needs on the dense path
 };
 
 struct mdt_batch_s {
@@ -146,10 +158,11 @@ struct mdt_batch_s {
     hipEvent_t staged = nullptr; // the last upload from h_stage has been consumed
     unsigned long long *d_counter = nullptr;
     int64_t ntiles = 0;
+    int32_t lds = 0;  // dynamic LDS of the persistent kernel (largest dense request)
     // captured launch
     hipGraphExec_t exec = nullptr;
     hipStream_t cap_stream = nullptr;
-    int graph_grid = -1, graph_policy = -1;
+    int graph_grid = -1, graph_policy = -1, graph_lds = -1;
     uint8_t *graph_buf = nullptr;
 };
 
@@ -232,8 +245,10 @@ int stage(mdt_batch_s *b, hipStream_t s)
     ReqDesc *D = (ReqDesc *)(b->h_stage + desc_off());
     int64_t *tile0 = (int64_t *)(b->h_stage + tile_off(b->cap));
     int64_t acc = 0;
+    b->lds = 0;
     for (size_t i = 0; i < b->reqs.size(); i++) {
         D[i] = b->reqs[i].d;
+        if (D[i].dense) b->lds = std::max(b->lds, b->reqs[i].lds);
         tile0[i] = acc;
         acc += (b->reqs[i].d.nchunks + T - 1) / T;
     }
@@ -266,9 +281,9 @@ void enqueue_kernels(mdt_batch_s *b, hipStream_t s, int grid)
     const int64_t *tile0 = (const int64_t *)(b->d_buf + tile_off(b->cap));
     if (b->cfg.policy == 1) {
         hipLaunchKernelGGL(batch_counter_reset, dim3(1), dim3(1), 0, s, b->d_counter);
-        hipLaunchKernelGGL(batch_kernel<1>, dim3(grid), dim3(256), 0, s, H, R, tile0, b->d_counter);
+        hipLaunchKernelGGL(batch_kernel<1>, dim3(grid), dim3(256), (size_t)b->lds, s, H, R, tile0, b->d_counter);
     } else {
-        hipLaunchKernelGGL(batch_kernel<0>, dim3(grid), dim3(256), 0, s, H, R, tile0, b->d_counter);
+        hipLaunchKernelGGL(batch_kernel<0>, dim3(grid), dim3(256), (size_t)b->lds, s, H, R, tile0, b->d_counter);
     }
 }
 
@@ -289,7 +304,8 @@ int launch(mdt_batch_s *b, hipStream_t s)
         }
         return MDT_SUCCESS;
     }
-    if (!b->exec || b->graph_grid != grid || b->graph_policy != b->cfg.policy || b->graph_buf != b->d_buf) {
+    if (!b->exec || b->graph_grid != grid || b->graph_policy != b->cfg.policy || b->graph_buf != b->d_buf ||
+        b->graph_lds != b->lds) {
         release_graph(b);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
@@ -306,6 +322,7 @@ int launch(mdt_batch_s *b, hipStream_t s)
         }
         b->graph_grid = grid;
         b->graph_policy = b->cfg.policy;
+        b->graph_lds = b->lds;
         b->graph_buf = b->d_buf;
     }
     hipError_t e = hipGraphLaunch(b->exec, s);
@@ -326,11 +343,11 @@ bool valid_cfg(const mdt_batch_config &c)
            (c.use_graph == 0 || c.use_graph == 1);
 }
 
-int add_req(mdt_batch b, TypeNode *t, const ReqDesc &d)
+int add_req(mdt_batch b, TypeNode *t, const ReqDesc &d, int32_t lds)
 {
     try {
         retain(t);
-        b->reqs.push_back({t, d});
+        b->reqs.push_back({t, d, lds});
     } catch (...) {
         release(t);
         return MDT_ERR_NO_MEM;
@@ -398,8 +415,10 @@ MDT_API int mdt_batch_add_pack(mdt_batch b, const void *inbuf, mdt_count incount
     if (n > 0 && (!inbuf || !outbuf)) return MDT_ERR_ARG;
     if (n > 0) {
         XferArgs A = make_args(inbuf, outbuf, inoffset, n);
-        ReqDesc d{D->d_lay, A.typed, A.packed, A.off, A.nbytes, A.head, A.nchunks, 0, D->lay.kind};
-        rc = add_req(b, reinterpret_cast<TypeNode *>(t), d);
+        A.elem1 = A.off + A.nbytes <= D->lay.size;
+        int dense = use_dense(D->lay, A, false);
+        ReqDesc d{D->d_lay, A.typed, A.packed, A.off, A.nbytes, A.head, A.nchunks, 0, D->lay.kind, A.elem1, dense};
+        rc = add_req(b, reinterpret_cast<TypeNode *>(t), d, dense ? D->lay.rec.lds_bytes : 0);
         if (rc) return rc;
     }
     *actual_pack_bytes = n;
@@ -421,8 +440,10 @@ MDT_API int mdt_batch_add_unpack(mdt_batch b, const void *inbuf, mdt_count insiz
     if (insize > 0 && (!inbuf || !outbuf)) return MDT_ERR_ARG;
     if (insize > 0) {
         XferArgs A = make_args(outbuf, const_cast<void *>(inbuf), outoffset, insize);
-        ReqDesc d{D->d_lay, A.typed, A.packed, A.off, A.nbytes, A.head, A.nchunks, 1, D->lay.kind};
-        rc = add_req(b, reinterpret_cast<TypeNode *>(t), d);
+        A.elem1 = A.off + A.nbytes <= D->lay.size;
+        int dense = use_dense(D->lay, A, true);
+        ReqDesc d{D->d_lay, A.typed, A.packed, A.off, A.nbytes, A.head, A.nchunks, 1, D->lay.kind, A.elem1, dense};
+        rc = add_req(b, reinterpret_cast<TypeNode *>(t), d, dense ? D->lay.rec.lds_bytes : 0);
         if (rc) return rc;
     }
     *actual_unpack_bytes = insize;

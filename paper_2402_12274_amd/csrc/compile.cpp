@@ -497,6 +497,14 @@ void lower_shape(const Shape &S, DevShape &D, Compiled &C)
         D.dspan[l] = make_magic((uint64_t)D.span[l]);
         D.drpi[l] = make_magic((uint64_t)D.rpi[l]);
     }
+    // 32-bit positions inside a group: every span and the group itself < 2^31
+    // (the group size is checked by the caller for fixed shapes)
+    bool small = !S.varlen && !S.implicit0;
+    for (size_t l = 0; l < S.loops.size(); l++) small = small && D.span[l] < ((int64_t)1 << 30);
+    if (small) {
+        for (size_t l = 0; l < S.loops.size(); l++) D.dspan32[l] = make_magic32((uint32_t)D.span[l]);
+    }
+    D.small32 = small;
     int64_t pre = 0;
     if (D.nleaf <= LEAFI) {
         for (int j = 0; j < D.nleaf; j++) {
@@ -653,6 +661,9 @@ void lower(TypeNode *t, const Layout &L, Compiled &C)
     for (size_t s = 0; s < L.shapes.size(); s++) lower_shape(L.shapes[s], C.shapes[s], C);
     set_leaf_ptrs(C);
     D.nshapes = (int32_t)L.shapes.size();
+    // a fixed shape's group holds the whole element: 32-bit positions need size < 2^31
+    for (size_t s = 0; s < C.shapes.size(); s++)
+        if (L.size >= ((int64_t)1 << 30)) C.shapes[s].small32 = 0;
     D.shape0 = C.shapes[0];
     D.G = (int64_t)G;
     D.nouter = (int32_t)L.outer.size();
@@ -830,7 +841,7 @@ void run_of_byte(const Compiled &C, int64_t q, int64_t *k, int64_t *start)
         q -= L.gpre[g];
         r += L.grpre[g];
         glen = L.gpre[g + 1] - L.gpre[g];
-        S = L.nshapes == 1 ? &L.shape0 : &L.shapes[L.gshape[g]];
+        S = &L.shapes[L.nshapes == 1 ? 0 : L.gshape[g]];
     }
     (void)glen;
     if (S->varlen) {
@@ -843,11 +854,10 @@ void run_of_byte(const Compiled &C, int64_t q, int64_t *k, int64_t *start)
         q -= i * S->span[l];
         r += i * S->rpi[l];
     }
-    const int64_t *pre = leaf_pre(*S);
     int j = 0;
-    while (j + 1 < S->nleaf && pre[j + 1] <= q) j++;
+    while (j + 1 < S->nleaf && leaf_at(*S, (uint64_t)(j + 1)).pre <= q) j++;
     *k = r + j;
-    *start = pos - (q - pre[j]);
+    *start = pos - (q - leaf_at(*S, (uint64_t)j).pre);
 }
 
 }  // namespace

@@ -16,6 +16,8 @@ struct XferArgs {
     int64_t head;          // packed & 15: the chunk grid is 16-byte aligned
     int64_t nchunks;       // 16-byte chunks covering [packed, packed + nbytes)
     int64_t tile_chunks;   // chunks per workgroup tile (0: default)
+    int32_t elem1;         // off + nbytes <= element size: only element 0 is touched
+    int32_t pad_;
 };
 
 XferArgs make_args(const void *typed, void *packed, int64_t off, int64_t nbytes);
@@ -23,5 +25,7 @@ int launch_xfer(const DevLayout &L, const XferArgs &A, bool unpack, hipStream_t 
 int launch_flatten(Compiled *c, DeviceTables *d, int64_t off, int64_t m, mdt_iov *out, const void *base,
                    hipStream_t s);
 int64_t default_tile_chunks(int64_t nchunks);
+// the dense record path applies to this request
+bool use_dense(const DevLayout &L, const XferArgs &A, bool unpack);
 
 }  // namespace mdt

@@ -157,10 +157,9 @@ __global__ __launch_bounds__(256) void xfer_kernel(const DevLayout L, const Xfer
 {
     int64_t c0 = xcd_tile() * A.tile_chunks;
     int64_t cend = c0 + A.tile_chunks < A.nchunks ? c0 + A.tile_chunks : A.nchunks;
-    for (int64_t c = c0 + threadIdx.x; c < cend; c += 256) {
-        if (UNPACK) unpack_chunk<KIND>(L, A, c);
-        else pack_chunk<KIND>(L, A, c);
-    }
+    // tile_chunks <= 1024: at most four chunks per lane
+    if (UNPACK) unpack_tile4<KIND>(L, A, c0, cend);
+    else pack_tile4<KIND>(L, A, c0, cend);
 }
 
 // dense record streams: one tile of chunks per workgroup, staged in LDS
@@ -225,6 +224,7 @@ int launch_xfer(const DevLayout &L, const XferArgs &A0, bool unpack, hipStream_t
 {
     if (A0.nbytes == 0 || L.kind == KIND_EMPTY) return MDT_SUCCESS;
     XferArgs A = A0;
+    A.elem1 = A.off + A.nbytes <= L.size;
     if (use_dense(L, A, unpack)) {
         A.tile_chunks = L.rec.tile_chunks;
         int64_t grid = (A.nchunks + A.tile_chunks - 1) / A.tile_chunks;
@@ -235,7 +235,7 @@ int launch_xfer(const DevLayout &L, const XferArgs &A0, bool unpack, hipStream_t
         HIPCHK(hipGetLastError());
         return MDT_SUCCESS;
     }
-    if (A.tile_chunks <= 0) A.tile_chunks = default_tile_chunks(A.nchunks);
+    if (A.tile_chunks <= 0 || A.tile_chunks > 1024) A.tile_chunks = default_tile_chunks(A.nchunks);
     int64_t grid = (A.nchunks + A.tile_chunks - 1) / A.tile_chunks;
     if (grid > 0x7fffffff) return MDT_ERR_ARG;
     dim3 g((unsigned)grid), b(256);
@@ -264,6 +264,7 @@ XferArgs make_args(const void *typed, void *packed, int64_t off, int64_t nbytes)
     A.head = (int64_t)((uintptr_t)packed & 15);
     A.nchunks = (A.head + nbytes + 15) / 16;
     A.tile_chunks = 0;
+    A.elem1 = 0;
     return A;
 }
 

@@ -73,26 +73,6 @@ inline MagicDiv make_magic(uint64_t d)
     return r;
 }
 
-struct DevShape {
-    int32_t nloops;     // inner loops, outer to inner
-    int32_t nleaf;      // leaf runs (0 when varlen)
-    int32_t varlen;     // the shape is one run as long as its group
-    int32_t implicit0;  // loop 0's count is the group length / span[0]
-    int64_t unit;       // packed bytes per innermost iteration (sum of leaf lengths)
-    int64_t span[MAXI];    // packed bytes per iteration of loop l
-    int64_t stride[MAXI];  // byte stride of loop l
-    int64_t cnt[MAXI];     // iteration count of loop l (loop 0: see implicit0)
-    int64_t rpi[MAXI];     // runs per iteration of loop l
-    MagicDiv dspan[MAXI];
-    MagicDiv drpi[MAXI];
-    int64_t loff[LEAFI];    // leaf run offsets (inline when nleaf <= LEAFI)
-    int64_t llen[LEAFI];
-    int64_t lpre[LEAFI + 1];  // leaf prefix: lpre[j] = sum of llen[0..j)
-    const int64_t *loff_p;  // leaf arrays when nleaf > LEAFI
-    const int64_t *llen_p;
-    const int64_t *lpre_p;
-};
-
 // n / d for 0 <= n < 2^31 and 1 <= d < 2^31 with a 32-bit high multiply:
 // m = ceil(2^(31+l) / d) < 2^32, q = mulhi(n, m) >> (l-1), l = ceil(log2 d).
 struct MagicDiv32 {
@@ -124,6 +104,29 @@ inline MagicDiv32 make_magic32(uint32_t d)
     r.s = l - 1;
     return r;
 }
+
+struct DevShape {
+    int32_t nloops;     // inner loops, outer to inner
+    int32_t nleaf;      // leaf runs (0 when varlen)
+    int32_t varlen;     // the shape is one run as long as its group
+    int32_t implicit0;  // loop 0's count is the group length / span[0]
+    int64_t unit;       // packed bytes per innermost iteration (sum of leaf lengths)
+    int64_t span[MAXI];    // packed bytes per iteration of loop l
+    int64_t stride[MAXI];  // byte stride of loop l
+    int64_t cnt[MAXI];     // iteration count of loop l (loop 0: see implicit0)
+    int64_t rpi[MAXI];     // runs per iteration of loop l
+    MagicDiv dspan[MAXI];
+    MagicDiv drpi[MAXI];
+    MagicDiv32 dspan32[MAXI];  // valid when small32
+    int32_t small32;           // every span < 2^31: positions inside a group fit 32 bits
+    int32_t pad_;
+    int64_t loff[LEAFI];    // leaf run offsets (inline when nleaf <= LEAFI)
+    int64_t llen[LEAFI];
+    int64_t lpre[LEAFI + 1];  // leaf prefix: lpre[j] = sum of llen[0..j)
+    const int64_t *loff_p;  // leaf arrays when nleaf > LEAFI
+    const int64_t *llen_p;
+    const int64_t *lpre_p;
+};
 
 // Record view: the packed stream is a sequence of equally spaced records
 // (element e at byte B0 + e*X), each holding the same leaf runs, U packed
@@ -193,9 +196,84 @@ struct Loc {
     int64_t rem;   // bytes left in its run, the located byte included
 };
 
-MDT_HD const int64_t *leaf_off(const DevShape &S) { return S.nleaf > LEAFI ? S.loff_p : S.loff; }
-MDT_HD const int64_t *leaf_len(const DevShape &S) { return S.nleaf > LEAFI ? S.llen_p : S.llen; }
-MDT_HD const int64_t *leaf_pre(const DevShape &S) { return S.nleaf > LEAFI ? S.lpre_p : S.lpre; }
+// The leaf run holding packed offset q of a shape's innermost body:
+// returns its offset, length and packed start.  Inline leaves are scanned
+// with static indices only (no pointer into the descriptor is formed, so a
+// descriptor passed as a kernel argument stays in the argument segment).
+struct Leaf {
+    int64_t off, len, pre;
+};
+
+MDT_HD Leaf leaf_of(const DevShape &S, uint64_t q)
+{
+    Leaf r;
+    if (S.nleaf > LEAFI) {
+        int lo = 0, hi = S.nleaf - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if ((uint64_t)S.lpre_p[mid] <= q) lo = mid; else hi = mid - 1;
+        }
+        r.off = S.loff_p[lo];
+        r.len = S.llen_p[lo];
+        r.pre = S.lpre_p[lo];
+        return r;
+    }
+    r.off = S.loff[0];
+    r.len = S.llen[0];
+    r.pre = 0;
+#pragma unroll
+    for (int i = 1; i < LEAFI; i++) {
+        if (i < S.nleaf && (uint64_t)S.lpre[i] <= q) {
+            r.off = S.loff[i];
+            r.len = S.llen[i];
+            r.pre = S.lpre[i];
+        }
+    }
+    return r;
+}
+
+// Leaf run number j (< nleaf): offset and length.
+MDT_HD Leaf leaf_at(const DevShape &S, uint64_t j)
+{
+    Leaf r;
+    if (S.nleaf > LEAFI) {
+        r.off = S.loff_p[j];
+        r.len = S.llen_p[j];
+        r.pre = S.lpre_p[j];
+        return r;
+    }
+    r.off = S.loff[0];
+    r.len = S.llen[0];
+    r.pre = 0;
+#pragma unroll
+    for (int i = 1; i < LEAFI; i++) {
+        if ((uint64_t)i == j) {
+            r.off = S.loff[i];
+            r.len = S.llen[i];
+            r.pre = S.lpre[i];
+        }
+    }
+    return r;
+}
+
+// Position q (< 2^31) inside a fixed shape whose spans all fit 32 bits.
+MDT_HD Loc locate_in_shape32(const DevShape &S, uint32_t q, int64_t addr)
+{
+    Loc r;
+#pragma unroll
+    for (int l = 0; l < MAXI; l++) {
+        if (l < S.nloops) {
+            uint32_t i = magic_div32(q, S.dspan32[l]);
+            q -= i * (uint32_t)S.span[l];
+            addr += (int64_t)i * S.stride[l];
+        }
+    }
+    Leaf f = leaf_of(S, q);
+    int64_t in = (int64_t)q - f.pre;
+    r.addr = addr + f.off + in;
+    r.rem = f.len - in;
+    return r;
+}
 
 // Position q inside one group of shape S (q < group length glen).
 MDT_HD Loc locate_in_shape(const DevShape &S, uint64_t q, int64_t glen, int64_t addr)
@@ -214,20 +292,10 @@ MDT_HD Loc locate_in_shape(const DevShape &S, uint64_t q, int64_t glen, int64_t 
             addr += (int64_t)i * S.stride[l];
         }
     }
-    const int64_t *pre = leaf_pre(S);
-    int j = 0;
-    if (S.nleaf > 1) {
-        // last j with pre[j] <= q
-        int lo = 0, hi = S.nleaf - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if ((uint64_t)pre[mid] <= q) lo = mid; else hi = mid - 1;
-        }
-        j = lo;
-    }
-    int64_t in = (int64_t)q - pre[j];
-    r.addr = addr + leaf_off(S)[j] + in;
-    r.rem = leaf_len(S)[j] - in;
+    Leaf f = leaf_of(S, q);
+    int64_t in = (int64_t)q - f.pre;
+    r.addr = addr + f.off + in;
+    r.rem = f.len - in;
     return r;
 }
 
@@ -244,9 +312,10 @@ MDT_HD int64_t find_group(const DevLayout &L, uint64_t q)
     return lo;
 }
 
-// Locate stream byte p (0 <= p < count*size) of (count x type).
+// Locate stream byte p (0 <= p < count*size) of (count x type).  elem1:
+// the caller guarantees p < size (only element 0 is touched).
 template <int KIND>
-MDT_HD Loc locate(const DevLayout &L, uint64_t p)
+MDT_HD Loc locate(const DevLayout &L, uint64_t p, bool elem1 = false)
 {
     Loc r;
     if (KIND == KIND_CONTIG) {
@@ -254,10 +323,11 @@ MDT_HD Loc locate(const DevLayout &L, uint64_t p)
         r.rem = INT64_MAX;
         return r;
     }
-    uint64_t e = magic_div(p, L.dsize);
+    uint64_t e = elem1 ? 0 : magic_div(p, L.dsize);
     uint64_t q = p - e * (uint64_t)L.size;
     int64_t addr = (int64_t)e * L.extent;
     if (KIND == KIND_SINGLE) {
+        if (L.shape0.small32) return locate_in_shape32(L.shape0, (uint32_t)q, addr + L.gdisp0);
         r = locate_in_shape(L.shape0, q, L.size, addr + L.gdisp0);
         return r;
     }
@@ -272,7 +342,8 @@ MDT_HD Loc locate(const DevLayout &L, uint64_t p)
     int64_t g = find_group(L, q);
     int64_t g0 = L.gpre[g];
     int64_t glen = L.gpre[g + 1] - g0;
-    const DevShape &S = L.nshapes == 1 ? L.shape0 : L.shapes[L.gshape[g]];
+    // shapes are read from the device table (never from the argument copy)
+    const DevShape &S = L.shapes[L.nshapes == 1 ? 0 : L.gshape[g]];
     return locate_in_shape(S, q - (uint64_t)g0, glen, addr + L.gdisp[g]);
 }
 
@@ -318,7 +389,7 @@ MDT_HD RunInfo run_at(const DevLayout &L, uint64_t k)
         k -= (uint64_t)L.grpre[lo];
         addr += L.gdisp[lo];
         glen = L.gpre[lo + 1] - L.gpre[lo];
-        S = L.nshapes == 1 ? &L.shape0 : &L.shapes[L.gshape[lo]];
+        S = &L.shapes[L.nshapes == 1 ? 0 : L.gshape[lo]];
     }
     if (S->varlen) {
         r.addr = addr;
@@ -333,8 +404,9 @@ MDT_HD RunInfo run_at(const DevLayout &L, uint64_t k)
             addr += (int64_t)i * S->stride[l];
         }
     }
-    r.addr = addr + leaf_off(*S)[k];
-    r.len = leaf_len(*S)[k];
+    Leaf f = leaf_at(*S, k);
+    r.addr = addr + f.off;
+    r.len = f.len;
     return r;
 }
 

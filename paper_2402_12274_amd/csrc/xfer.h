@@ -19,26 +19,22 @@ struct V4 {
     uint32_t w0, w1, w2, w3;
 };
 
-// word i (0..3, 4 reads as 3) of the chunk, by two levels of selects (a
-// compare chain would be turned into an indexed stack array)
-__device__ __forceinline__ uint32_t sel(const V4 &a, int i)
+// Byte / dword extraction at a variable byte position of the chunk, as
+// 128-bit shifts (funnel shifts in registers; an indexed select would be
+// turned into a per-lane memory array).
+__device__ __forceinline__ unsigned __int128 as128(const V4 &a)
 {
-    uint32_t lo = (i & 1) ? a.w1 : a.w0;
-    uint32_t hi = (i & 1) ? a.w3 : a.w2;
-    return (i & 2) ? hi : (i & 4) ? a.w3 : lo;
+    return ((unsigned __int128)a.w3 << 96) | ((unsigned __int128)a.w2 << 64) | ((unsigned __int128)a.w1 << 32) |
+           (unsigned __int128)a.w0;
 }
 
 __device__ __forceinline__ uint32_t byte_at(const V4 &a, int pos)
 {
-    return (sel(a, pos >> 2) >> (8 * (pos & 3))) & 0xffu;
+    return (uint32_t)(as128(a) >> (8 * pos)) & 0xffu;
 }
 
 // 4 bytes starting at byte pos (0 <= pos <= 12) of the 16-byte chunk
-__device__ __forceinline__ uint32_t dword_at(const V4 &a, int pos)
-{
-    int w = pos >> 2;
-    return __builtin_amdgcn_alignbyte(sel(a, w + 1), sel(a, w), (uint32_t)(pos & 3));
-}
+__device__ __forceinline__ uint32_t dword_at(const V4 &a, int pos) { return (uint32_t)(as128(a) >> (8 * pos)); }
 
 // 16 bytes from an arbitrarily aligned source; every dword loaded holds at
 // least one of the 16 bytes, so no access leaves the source's pages.
@@ -68,26 +64,30 @@ __device__ __forceinline__ V4 load16(const uint8_t *s)
     return r;
 }
 
+// The part of chunk word t (bytes 4t..4t+3) that bytes s[0..n), placed at
+// chunk positions [k, k+n), contribute.
+__device__ __forceinline__ uint32_t gather_word(int t, int k, const uint8_t *s, int n)
+{
+    int a = max(4 * t, k), b = min(4 * t + 4, k + n);
+    if (a >= b) return 0u;
+    uintptr_t u = (uintptr_t)(s + (a - k));
+    const uint32_t *p = (const uint32_t *)(u & ~(uintptr_t)3);
+    uint32_t sh = (uint32_t)(u & 3);
+    int cnt = b - a;
+    uint32_t lo = p[0];
+    uint32_t hi = ((int)sh + cnt > 4) ? p[1] : 0u;
+    uint32_t v = __builtin_amdgcn_alignbyte(hi, lo, sh);
+    uint32_t m = cnt >= 4 ? 0xffffffffu : ((1u << (8 * cnt)) - 1u);
+    return (v & m) << (8 * (a - 4 * t));
+}
+
 // OR bytes s[0..n) into chunk positions [k, k+n)  (n < 16 or k > 0)
 __device__ __forceinline__ void gather_part(V4 &acc, int k, const uint8_t *s, int n)
 {
-    uint32_t out[4] = {acc.w0, acc.w1, acc.w2, acc.w3};
-#pragma unroll
-    for (int t = 0; t < 4; t++) {
-        int a = max(4 * t, k), b = min(4 * t + 4, k + n);
-        if (a < b) {
-            uintptr_t u = (uintptr_t)(s + (a - k));
-            const uint32_t *p = (const uint32_t *)(u & ~(uintptr_t)3);
-            uint32_t sh = (uint32_t)(u & 3);
-            int cnt = b - a;
-            uint32_t lo = p[0];
-            uint32_t hi = ((int)sh + cnt > 4) ? p[1] : 0u;
-            uint32_t v = __builtin_amdgcn_alignbyte(hi, lo, sh);
-            uint32_t m = cnt >= 4 ? 0xffffffffu : ((1u << (8 * cnt)) - 1u);
-            out[t] |= (v & m) << (8 * (a - 4 * t));
-        }
-    }
-    acc.w0 = out[0]; acc.w1 = out[1]; acc.w2 = out[2]; acc.w3 = out[3];
+    acc.w0 |= gather_word(0, k, s, n);
+    acc.w1 |= gather_word(1, k, s, n);
+    acc.w2 |= gather_word(2, k, s, n);
+    acc.w3 |= gather_word(3, k, s, n);
 }
 
 // write chunk bytes [k, k+n) to d[0..n): only those bytes are stored
@@ -134,7 +134,7 @@ __device__ __forceinline__ void pack_chunk(const DevLayout &L, const XferArgs &A
     uint64_t p = (uint64_t)(A.off + a);
     V4 acc = {0u, 0u, 0u, 0u};
     const uint8_t *src = A.typed;
-    Loc l = locate<KIND>(L, p);
+    Loc l = locate<KIND>(L, p, A.elem1);
     if (n == 16 && l.rem >= 16) {
         acc = load16(src + l.addr);
     } else {
@@ -146,7 +146,7 @@ __device__ __forceinline__ void pack_chunk(const DevLayout &L, const XferArgs &A
             k += take;
             n -= take;
             if (n <= 0) break;
-            l = locate<KIND>(L, p);
+            l = locate<KIND>(L, p, A.elem1);
         }
     }
     uint8_t *dst = A.packed - A.head + 16 * c;
@@ -172,7 +172,7 @@ __device__ __forceinline__ void unpack_chunk(const DevLayout &L, const XferArgs 
     V4 acc = {v.x, v.y, v.z, v.w};
     uint64_t p = (uint64_t)(A.off + a);
     uint8_t *dst = const_cast<uint8_t *>(A.typed);
-    Loc l = locate<KIND>(L, p);
+    Loc l = locate<KIND>(L, p, A.elem1);
     for (;;) {
         int take = l.rem < n ? (int)l.rem : n;
         if (take <= 0) break;  // unreachable for a well-formed layout; never spin
@@ -181,7 +181,90 @@ __device__ __forceinline__ void unpack_chunk(const DevLayout &L, const XferArgs 
         k += take;
         n -= take;
         if (n <= 0) break;
-        l = locate<KIND>(L, p);
+        l = locate<KIND>(L, p, A.elem1);
+    }
+}
+
+// A lane's chunks c0 + lane + 256k (k < 4) of a tile, loads first: every
+// chunk whose 16 bytes lie in one run is loaded before any store is issued,
+// so up to four gathers per lane are in flight at once.  Other chunks take
+// the general body.
+template <int KIND>
+__device__ __forceinline__ bool pack_first(const DevLayout &L, const XferArgs &A, int64_t c, int64_t cend, V4 &acc)
+{
+    int64_t lo = 16 * c - A.head;
+    if (c < cend && lo >= 0 && lo + 16 <= A.nbytes) {
+        Loc l = locate<KIND>(L, (uint64_t)(A.off + lo), A.elem1);
+        if (l.rem >= 16) {
+            acc = load16(A.typed + l.addr);
+            return true;
+        }
+    }
+    return false;
+}
+
+__device__ __forceinline__ void store_chunk(const XferArgs &A, int64_t c, const V4 &acc)
+{
+    u32x4 v = {acc.w0, acc.w1, acc.w2, acc.w3};
+    __builtin_nontemporal_store(v, (u32x4 *)(A.packed - A.head + 16 * c));
+}
+
+// A lane's chunks c0 + lane + 256k (k < 4) of a tile, loads first: every
+// chunk whose 16 bytes lie in one run is loaded before any store is issued,
+// so up to four gathers per lane are in flight at once.  The other chunks
+// then take the general body, one at a time.
+template <int KIND>
+__device__ __forceinline__ void pack_tile4(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t cend)
+{
+    const int64_t c = c0 + threadIdx.x;
+    V4 a0 = {0u, 0u, 0u, 0u}, a1 = a0, a2 = a0, a3 = a0;
+    uint32_t fast = (uint32_t)pack_first<KIND>(L, A, c, cend, a0) | (uint32_t)pack_first<KIND>(L, A, c + 256, cend, a1) << 1 |
+                    (uint32_t)pack_first<KIND>(L, A, c + 512, cend, a2) << 2 |
+                    (uint32_t)pack_first<KIND>(L, A, c + 768, cend, a3) << 3;
+    if (fast & 1u) store_chunk(A, c, a0);
+    if (fast & 2u) store_chunk(A, c + 256, a1);
+    if (fast & 4u) store_chunk(A, c + 512, a2);
+    if (fast & 8u) store_chunk(A, c + 768, a3);
+#pragma unroll 1
+    for (int k = 0; k < 4; k++) {
+        int64_t ck = c + 256 * k;
+        if (ck < cend && !((fast >> k) & 1u)) pack_chunk<KIND>(L, A, ck);
+    }
+}
+
+template <int KIND>
+__device__ __forceinline__ bool unpack_first(const DevLayout &L, const XferArgs &A, int64_t c, int64_t cend, V4 &acc,
+                                             Loc &loc)
+{
+    int64_t lo = 16 * c - A.head;
+    if (c < cend && lo >= 0 && lo + 16 <= A.nbytes) {
+        u32x4 v = __builtin_nontemporal_load((const u32x4 *)(A.packed - A.head + 16 * c));
+        acc = V4{v.x, v.y, v.z, v.w};
+        loc = locate<KIND>(L, (uint64_t)(A.off + lo), A.elem1);
+        return loc.rem >= 16;
+    }
+    return false;
+}
+
+template <int KIND>
+__device__ __forceinline__ void unpack_tile4(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t cend)
+{
+    const int64_t c = c0 + threadIdx.x;
+    uint8_t *dst = const_cast<uint8_t *>(A.typed);
+    V4 a0 = {0u, 0u, 0u, 0u}, a1 = a0, a2 = a0, a3 = a0;
+    Loc l0 = {0, 0}, l1 = l0, l2 = l0, l3 = l0;
+    uint32_t fast = (uint32_t)unpack_first<KIND>(L, A, c, cend, a0, l0) |
+                    (uint32_t)unpack_first<KIND>(L, A, c + 256, cend, a1, l1) << 1 |
+                    (uint32_t)unpack_first<KIND>(L, A, c + 512, cend, a2, l2) << 2 |
+                    (uint32_t)unpack_first<KIND>(L, A, c + 768, cend, a3, l3) << 3;
+    if (fast & 1u) scatter(a0, 0, dst + l0.addr, 16);
+    if (fast & 2u) scatter(a1, 0, dst + l1.addr, 16);
+    if (fast & 4u) scatter(a2, 0, dst + l2.addr, 16);
+    if (fast & 8u) scatter(a3, 0, dst + l3.addr, 16);
+#pragma unroll 1
+    for (int k = 0; k < 4; k++) {
+        int64_t ck = c + 256 * k;
+        if (ck < cend && !((fast >> k) & 1u)) unpack_chunk<KIND>(L, A, ck);
     }
 }
 
@@ -229,6 +312,33 @@ __device__ __forceinline__ uint32_t stage_span(uint8_t *lds, const uint8_t *g_lo
     return (uint32_t)((uintptr_t)g_lo - a);
 }
 
+// Next packed word of a dense record stream: q is the packed offset inside
+// record er (relative to the tile's first record); both advance by 4.
+__device__ __forceinline__ uint32_t dense_word(const uint32_t *tab, const uint8_t *span, uint32_t base, uint32_t X,
+                                               uint32_t U, uint32_t &q, uint32_t &er)
+{
+    uint32_t e = tab[q];
+    if ((e >> 16) >= 4u) {
+        uint32_t w = lds_u32(span, base + er * X + (e & 0xffffu));
+        q += 4;
+        if (q == U) {
+            q = 0;
+            er++;
+        }
+        return w;
+    }
+    uint32_t v = 0;
+    for (int i = 0; i < 4; i++) {
+        uint32_t ei = tab[q];
+        v |= lds_u8(span, base + er * X + (ei & 0xffffu)) << (8 * i);
+        if (++q == U) {
+            q = 0;
+            er++;
+        }
+    }
+    return v;
+}
+
 // Pack chunks [c0, c1) of A (a tile) with the record view of L.  `lds`
 // holds rec.lds_bytes of dynamic shared memory.
 __device__ __forceinline__ void dense_pack_tile(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t c1,
@@ -257,27 +367,12 @@ __device__ __forceinline__ void dense_pack_tile(const DevLayout &L, const XferAr
         uint32_t rel = (uint32_t)(a - P_lo) + q0;
         uint32_t er = magic_div32(rel, R.dU32);
         uint32_t q = rel - er * U;
-        uint32_t w[4] = {0u, 0u, 0u, 0u};
         if (a == lo && b == lo + 16) {
-#pragma unroll
-            for (int t = 0; t < 4; t++) {
-                uint32_t e = tab[q];
-                if ((e >> 16) >= 4u) {
-                    w[t] = lds_u32(span, base + er * X + (e & 0xffffu));
-                    q += 4;
-                    if (q == U) { q = 0; er++; }
-                } else {
-                    uint32_t v = 0;
-#pragma unroll
-                    for (int i = 0; i < 4; i++) {
-                        uint32_t ei = tab[q];
-                        v |= lds_u8(span, base + er * X + (ei & 0xffffu)) << (8 * i);
-                        if (++q == U) { q = 0; er++; }
-                    }
-                    w[t] = v;
-                }
-            }
-            u32x4 v = {w[0], w[1], w[2], w[3]};
+            uint32_t w0 = dense_word(tab, span, base, X, U, q, er);
+            uint32_t w1 = dense_word(tab, span, base, X, U, q, er);
+            uint32_t w2 = dense_word(tab, span, base, X, U, q, er);
+            uint32_t w3 = dense_word(tab, span, base, X, U, q, er);
+            u32x4 v = {w0, w1, w2, w3};
             __builtin_nontemporal_store(v, (u32x4 *)(A.packed - A.head + 16 * c));
         } else {
             uint8_t *dst = A.packed - A.head + 16 * c;

@@ -49,6 +49,36 @@ int main()
         check(top, d + 1);
         check(top, d - 1 ? d - 1 : 1);
     }
+    // 32-bit variant: n < 2^31, 1 <= d < 2^31
+    auto check32 = [&](uint32_t n, uint32_t d) {
+        mdt::MagicDiv32 m = mdt::make_magic32(d);
+        uint32_t q = mdt::magic_div32(n, m);
+        checked++;
+        if (q != n / d) {
+            if (bad < 10) std::printf("bad32 n=%u d=%u got %u want %u\n", n, d, q, n / d);
+            bad++;
+        }
+    };
+    const uint32_t top32 = 0x7fffffffu;
+    for (uint32_t d = 1; d < 5000; d++) {
+        for (uint32_t k = 0; k < 40; k++) {
+            uint64_t n = (uint64_t)d * k;
+            if (n > top32) break;
+            check32((uint32_t)n, d);
+            if (n) check32((uint32_t)n - 1, d);
+            if (n < top32) check32((uint32_t)n + 1, d);
+        }
+        check32(top32, d);
+        for (int i = 0; i < 40; i++) check32((uint32_t)(g() & top32), d);
+    }
+    for (int i = 0; i < 2000000; i++) {
+        uint32_t d = (uint32_t)(g() % top32) + 1;
+        uint32_t n = (uint32_t)(g() & top32);
+        check32(n, d);
+        uint32_t k = n / d;
+        check32(k * d, d);
+        if (k) check32(k * d - 1, d);
+    }
     std::printf("checked %ld bad %ld\n", checked, bad);
     return bad != 0;
 }
