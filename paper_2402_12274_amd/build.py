@@ -11,6 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmdt.so")
+LOADGEN = os.path.join(HERE, "libmdt_loadgen.so")
 
 SOURCES = ["types.cpp", "compile.cpp", "api.cpp", "device.hip", "batch.hip", "server.cpp"]
 ARCH = os.environ.get("MDT_OFFLOAD_ARCH", "gfx950")
@@ -44,6 +45,14 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    # open-loop load generator for the serving benchmark (public C ABI only)
+    lg_obj = _compile("loadgen.cpp")
+    tmp = LOADGEN + ".tmp"
+    cmd = ["hipcc", "-shared", "-fPIC", "-o", tmp, lg_obj, LIB, "-Wl,-rpath,$ORIGIN", "-lpthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, LOADGEN)
     if verbose:
         print(f"built {LIB}")
     return LIB

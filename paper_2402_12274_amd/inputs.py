@@ -144,3 +144,51 @@ def batch_mix(nreq: int = 4096, seed: int = DEFAULT_SEED, lo: int = 64, hi: int 
         else:
             reqs.append(dict(kind="hindexed", spec_key=("hindexed",), target=int(sizes[i]), spec=None))
     return reqs
+
+
+# ---------------------------------------------------------------------------
+# serving trace
+
+
+def serving_types(seed: int = DEFAULT_SEED, ntypes: int = 500):
+    """Resident types of the serving workload: (family, spec) pairs drawn from
+    strided float64 vectors, halo faces of 128^3..512^3 arrays, hindexed
+    layouts with 4k..64k blocks inside 256 MiB, and particle-like records."""
+    g = rng(seed)
+    out = []
+    fams = ["vector", "face", "hindexed", "struct"]
+    for i in range(ntypes):
+        fam = fams[i % 4]
+        if fam == "vector":
+            n = int(2 ** g.integers(12, 17))
+            out.append((fam, ("vector", n, 1, int(g.integers(2, 65)), DOUBLE)))
+        elif fam == "face":
+            n = int(g.choice([128, 192, 256, 384, 512]))
+            w = int(g.integers(1, 5))
+            out.append((fam, halo_face(n, w, int(g.integers(0, 3)), "lo" if g.random() < 0.5 else "hi")))
+        elif fam == "hindexed":
+            nb = int(g.integers(4096, 65537))
+            lens, disps = hindexed_blocks(nblocks=nb, span=1 << 28, seed=int(g.integers(0, 1 << 30)))
+            out.append((fam, hindexed_type(lens, disps)))
+        else:
+            k = int(g.integers(1, 6))
+            out.append((fam, ("struct", [1, k, 5], [0, 8, 8 + 8 * k], [("basic", "INT32"), DOUBLE, ("basic", "CHAR")])))
+    return out
+
+
+def serving_trace(rate: float, duration_s: float, ntypes: int, seed: int = DEFAULT_SEED, zipf_s: float = 1.2,
+                  unit: int = 256, kmax: int = 262144):
+    """Open-loop trace: Poisson arrival times (us), pack/unpack 50/50, type
+    index uniform, requested packed bytes = unit * k with k ~ Zipf(zipf_s)
+    rejected above kmax (256 B .. 64 MiB)."""
+    g = rng(seed + 17)
+    n = int(rate * duration_s * 1.1) + 16
+    t = np.cumsum(g.exponential(1e6 / rate, size=n))
+    t = t[t < duration_s * 1e6]
+    n = t.size
+    k = g.zipf(zipf_s, size=n)
+    while (k > kmax).any():
+        bad = k > kmax
+        k[bad] = g.zipf(zipf_s, size=int(bad.sum()))
+    return dict(t_us=t, unpack=g.integers(0, 2, size=n).astype(np.int32),
+                type_index=g.integers(0, ntypes, size=n).astype(np.int32), target=(unit * k).astype(np.int64))
