@@ -42,10 +42,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="halo",
-                    choices=["halo", "particles", "hindexed", "contig", "small", "serve", "batch4096"])
+                    choices=["halo", "particles", "hindexed", "contig", "rows", "small", "serve", "batch4096"])
     ap.add_argument("--duration", type=float, default=15.0, help="serve: seconds of trace per replay")
     ap.add_argument("--rate", type=float, default=20000.0, help="serve: Poisson arrival rate (requests/s)")
-    ap.add_argument("--mode", default="plain", choices=["plain", "batched"])
+    ap.add_argument("--mode", default="batched", choices=["plain", "batched"])
     ap.add_argument("--rotate", type=int, default=4,
                     help="rotate over this many copies of the arrays so every step reads cold data")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -79,6 +79,12 @@ def workload(name):
         return dict(desc="contiguous: 2^27 float64 (1 GiB), packed then unpacked per step",
                     src_bytes=1 << 30, reqs=[("contig", ("contiguous", 1 << 27, inputs.DOUBLE), 1)],
                     seed=inputs.DEFAULT_SEED + 3)
+    if name == "rows":
+        n, w = 8192, 64
+        spec = ("subarray", [n, n], [n - 2 * w, n - 2 * w], [w, w], "C", inputs.DOUBLE)
+        return dict(desc="row-dominated subarray: interior [64, 8128)^2 block of a float64 8192x8192 array "
+                         "(512 MiB): 8064 rows of 64,512 B, packed then unpacked per step",
+                    src_bytes=n * n * 8, reqs=[("rows", spec, 1)], seed=inputs.DEFAULT_SEED + 4)
     if name == "small":
         return dict(desc="small vector: vector(1024, 1, 2, float64), 8 KiB packed from 16 KiB, packed then "
                          "unpacked per step", src_bytes=16384, reqs=[("vector", inputs.vector_small(), 1)],
@@ -340,11 +346,15 @@ def main():
             bp.set_config(bp0.get_config())
             bu.set_config(bu0.get_config())
 
-    # per-kernel event timing of the pack direction and the unpack direction
-    ev_log = {"pack": [], "unpack": []}
+    # HIP events around every launch on the launch stream, grouped by kernel
+    # (batched: one persistent kernel for both directions; plain: per direction)
+    ev_log = {}
 
-    def step(r, timed):
-        if batches is not None:
+    def log(name, e0, e1, nbytes):
+        ev_log.setdefault(name, []).append((e0, e1, nbytes))
+
+    def step(r, timed, batched):
+        if batched:
             bp, bu = batches[r]
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -355,8 +365,8 @@ def main():
             bu.launch(ms)
             e2.record(stream)
             if timed:
-                ev_log["pack"].append((e0, e1, sum(sizes)))
-                ev_log["unpack"].append((e1, e2, sum(sizes)))
+                log("batch_kernel (pack and unpack launches)", e0, e1, sum(sizes))
+                log("batch_kernel (pack and unpack launches)", e1, e2, sum(sizes))
             return
         for (label, t, count), out, s in zip(types, packed[r], sizes):
             e0 = torch.cuda.Event(enable_timing=True)
@@ -365,7 +375,7 @@ def main():
             mdt.mdt_pack_enqueue(srcs[r].data_ptr(), count, t, 0, out.data_ptr(), -1, ms)
             e1.record(stream)
             if timed:
-                ev_log["pack"].append((e0, e1, s))
+                log("pack launches", e0, e1, s)
         for (label, t, count), out, s in zip(types, packed[r], sizes):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -373,20 +383,27 @@ def main():
             mdt.mdt_unpack_enqueue(out.data_ptr(), s, dsts[r].data_ptr(), count, t, 0, ms)
             e1.record(stream)
             if timed:
-                ev_log["unpack"].append((e0, e1, s))
+                log("unpack launches", e0, e1, s)
 
-    for i in range(args.warmup):
-        step(i % R, False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(i % R, True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    def timed_run(batched, record):
+        for i in range(args.warmup):
+            step(i % R, False, batched)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            step(i % R, record, batched)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
 
+    dt = timed_run(batches is not None, True)
     value = step_bytes * args.steps / dt / 1e9
+    other = None
+    if batches is not None:
+        dt_plain = timed_run(False, False)
+        other = {"mode": "plain (one launch per request)", "value": round(step_bytes * args.steps / dt_plain / 1e9, 2),
+                 "ms_per_step": round(dt_plain / args.steps * 1e3, 4)}
     copy_ceiling = copy_ceiling_gbs(torch, dev)
-    # dominant direction: the one with the larger total kernel time
+    # dominant kernel: the one with the larger total kernel time
     per = {}
     for k, lst in ev_log.items():
         durs = [a.elapsed_time(b) * 1e-3 for a, b, _ in lst]
@@ -416,9 +433,11 @@ def main():
                    "device_copy_ceiling_GBps": copy_ceiling},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                     "kernel": f"{dom} ({'batched launch' if batches else 'one launch per request'})",
+                     "kernel": dom,
                      "avg_launch_us": round(avg_dur * 1e6, 2), "bytes_per_launch": int(bytes_per_launch)},
     }
+    if other is not None:
+        out["per_request"] = other
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
     print(json.dumps(out), flush=True)

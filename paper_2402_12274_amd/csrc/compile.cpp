@@ -722,6 +722,7 @@ void lower(TypeNode *t, const Layout &L, Compiled &C)
             orun *= L.outer[l].cnt;
         }
         D.nruns = orun;
+        D.runs_only = L.outer.empty() && L.shapes.size() == 1 && L.shapes[0].varlen;
         D.gdisp = C.gdisp.data();
         D.gpre = C.gpre.data();
         D.grpre = C.grpre.data();

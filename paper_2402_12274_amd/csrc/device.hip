@@ -173,6 +173,16 @@ __global__ __launch_bounds__(256) void dense_kernel(const DevLayout L, const Xfe
     else dense_pack_tile(L, A, c0, c1, lds_dyn);
 }
 
+// run tables: tile of chunks with the tile's groups cached in LDS
+template <bool UNPACK>
+__global__ __launch_bounds__(256) void runs_kernel(const DevLayout L, const XferArgs A)
+{
+    __shared__ RunsCache cache;
+    int64_t c0 = xcd_tile() * A.tile_chunks;
+    int64_t c1 = c0 + A.tile_chunks < A.nchunks ? c0 + A.tile_chunks : A.nchunks;
+    runs_tile<UNPACK>(L, A, c0, c1, cache);
+}
+
 // flatten: one lane per segment
 __global__ __launch_bounds__(256) void flatten_kernel(const DevLayout L, int64_t off, int64_t m, mdt_iov *out,
                                                      uintptr_t base)
@@ -212,6 +222,15 @@ static bool dense_enabled()
     return on;
 }
 
+static bool runs_enabled()
+{
+    static const bool on = [] {
+        const char *e = getenv("MDT_RUNS_CACHE");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
 bool use_dense(const DevLayout &L, const XferArgs &A, bool unpack)
 {
     const DevRecords &R = L.rec;
@@ -232,6 +251,15 @@ int launch_xfer(const DevLayout &L, const XferArgs &A0, bool unpack, hipStream_t
         size_t lds = (size_t)L.rec.lds_bytes;
         if (unpack) hipLaunchKernelGGL(dense_kernel<true>, dim3((unsigned)grid), dim3(256), lds, s, L, A);
         else hipLaunchKernelGGL(dense_kernel<false>, dim3((unsigned)grid), dim3(256), lds, s, L, A);
+        HIPCHK(hipGetLastError());
+        return MDT_SUCCESS;
+    }
+    if (L.kind == KIND_MULTI && L.runs_only && runs_enabled()) {
+        A.tile_chunks = 1024;
+        int64_t grid = (A.nchunks + A.tile_chunks - 1) / A.tile_chunks;
+        if (grid > 0x7fffffff) return MDT_ERR_ARG;
+        if (unpack) hipLaunchKernelGGL(runs_kernel<true>, dim3((unsigned)grid), dim3(256), 0, s, L, A);
+        else hipLaunchKernelGGL(runs_kernel<false>, dim3((unsigned)grid), dim3(256), 0, s, L, A);
         HIPCHK(hipGetLastError());
         return MDT_SUCCESS;
     }

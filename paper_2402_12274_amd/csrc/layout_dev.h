@@ -179,6 +179,8 @@ struct DevLayout {
     int64_t gdisp0;         // displacement of group 0 (KIND_CONTIG / KIND_SINGLE)
     int32_t nshapes;
     int32_t dir_shift;      // directory granularity = 1 << dir_shift packed bytes
+    int32_t runs_only;      // every group is a single run (varlen shape), no outer loops
+    int32_t pad1_;
     int64_t ndir;           // directory entries
     const int64_t *gdisp;   // [G]   group displacement
     const int64_t *gpre;    // [G+1] packed-byte prefix of groups

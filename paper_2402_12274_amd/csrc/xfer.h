@@ -443,3 +443,110 @@ __device__ __forceinline__ void dense_unpack_tile(const DevLayout &L, const Xfer
 }
 
 }  // namespace mdt
+
+namespace mdt {
+
+// ---------------------------------------------------------------------------
+// run tables (every group one run, e.g. hindexed of bytes): a workgroup
+// caches its tile's slice of the group prefix and displacement tables in LDS
+// so each lane finds its run by an LDS binary search instead of a chain of
+// dependent global loads.
+
+constexpr int RUNS_CACHE = 2048;
+
+struct RunsCache {
+    int64_t pre[RUNS_CACHE + 1];
+    int64_t disp[RUNS_CACHE];
+};
+
+// Load groups covering stream bytes [s_lo, s_hi) of one element into C.
+// Returns the number of cached groups, or -1 when the tile does not fit
+// (several elements, or more groups than the cache holds).
+__device__ __forceinline__ int64_t runs_cache_fill(const DevLayout &L, const XferArgs &A, uint64_t s_lo, uint64_t s_hi,
+                                                   RunsCache &C, int64_t &g0, uint64_t &ebase, int64_t &eaddr)
+{
+    uint64_t e0 = A.elem1 ? 0 : magic_div(s_lo, L.dsize);
+    uint64_t e1 = A.elem1 ? 0 : magic_div(s_hi - 1, L.dsize);
+    if (e0 != e1) return -1;
+    ebase = e0 * (uint64_t)L.size;
+    eaddr = (int64_t)e0 * L.extent;
+    g0 = find_group(L, s_lo - ebase);
+    int64_t g1 = find_group(L, s_hi - 1 - ebase);
+    int64_t n = g1 - g0 + 1;
+    if (n > RUNS_CACHE) return -1;
+    for (int64_t i = threadIdx.x; i <= n; i += blockDim.x) C.pre[i] = L.gpre[g0 + i];
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) C.disp[i] = L.gdisp[g0 + i];
+    __syncthreads();
+    return n;
+}
+
+// cached group holding element-relative position q
+__device__ __forceinline__ int runs_find(const RunsCache &C, int n, uint64_t q)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if ((uint64_t)C.pre[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <bool UNPACK>
+__device__ __forceinline__ void runs_tile(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t c1, RunsCache &C)
+{
+    const int64_t P_lo = max(16 * c0 - A.head, (int64_t)0);
+    const int64_t P_hi = min(16 * c1 - A.head, A.nbytes);
+    int64_t g0;
+    uint64_t ebase;
+    int64_t eaddr;
+    int64_t n = runs_cache_fill(L, A, (uint64_t)(A.off + P_lo), (uint64_t)(A.off + P_hi), C, g0, ebase, eaddr);
+    if (n < 0) {
+        if (UNPACK) {
+            for (int64_t s0 = c0; s0 < c1; s0 += 1024) unpack_tile4<KIND_MULTI>(L, A, s0, min(s0 + 1024, c1));
+        } else {
+            for (int64_t s0 = c0; s0 < c1; s0 += 1024) pack_tile4<KIND_MULTI>(L, A, s0, min(s0 + 1024, c1));
+        }
+        return;
+    }
+    const uint8_t *typed = A.typed;
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+        const int64_t lo = 16 * c - A.head;
+        const int64_t a = lo > 0 ? lo : 0;
+        const int64_t b = lo + 16 < A.nbytes ? lo + 16 : A.nbytes;
+        int k = (int)(a - lo), m = (int)(b - a);
+        uint64_t q = (uint64_t)(A.off + a) - ebase;
+        int i = runs_find(C, (int)n, q);
+        V4 acc = {0u, 0u, 0u, 0u};
+        if (UNPACK) {
+            u32x4 v = __builtin_nontemporal_load((const u32x4 *)(A.packed - A.head + 16 * c));
+            acc = V4{v.x, v.y, v.z, v.w};
+        }
+        while (m > 0) {
+            int64_t in = (int64_t)q - C.pre[i];
+            int64_t rem = C.pre[i + 1] - (int64_t)q;
+            int take = rem < m ? (int)rem : m;
+            const int64_t addr = eaddr + C.disp[i] + in;
+            if (UNPACK) {
+                scatter(acc, k, const_cast<uint8_t *>(typed) + addr, take);
+            } else {
+                if (take == 16) acc = load16(typed + addr);
+                else gather_part(acc, k, typed + addr, take);
+            }
+            q += take;
+            k += take;
+            m -= take;
+            i++;
+        }
+        if (!UNPACK) {
+            uint8_t *dst = A.packed - A.head + 16 * c;
+            if (a == lo && b == lo + 16) {
+                u32x4 v = {acc.w0, acc.w1, acc.w2, acc.w3};
+                __builtin_nontemporal_store(v, (u32x4 *)dst);
+            } else {
+                for (int j = (int)(a - lo); j < (int)(b - lo); j++) dst[j] = (uint8_t)byte_at(acc, j);
+            }
+        }
+    }
+}
+
+}  // namespace mdt
