@@ -22,6 +22,15 @@ LIB_PATH = os.path.join(_HERE, "libmdt.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2402_12274_amd.build`")
 
+# One HIP runtime per process: PyTorch ships its own libamdhip64 and loads it
+# under a name the dynamic loader does not match against an already loaded
+# system copy, so torch (when present) is imported first and libmdt then
+# binds to that same runtime by soname.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _lib = C.CDLL(LIB_PATH)
 
 # error codes (include/mdt.h)

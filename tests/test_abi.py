@@ -42,3 +42,16 @@ def test_plain_c_client():
         r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
         assert r.returncode == 0, r.stdout + r.stderr
         assert "abi ok" in r.stdout
+
+
+def test_one_hip_runtime_per_process():
+    """Importing the binding before torch must not load a second HIP runtime
+    (a second runtime sees no device)."""
+    import subprocess
+    import sys
+
+    code = ("import paper_2402_12274_amd.mdt, torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n")
+    out = subprocess.check_output([sys.executable, "-c", code], cwd=ROOT, text=True, timeout=300)
+    assert out.strip().splitlines()[-1] == "1"
