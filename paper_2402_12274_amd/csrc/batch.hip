@@ -46,6 +46,35 @@ struct BatchHeader {
 
 constexpr int LAY_WORDS = (int)((sizeof(DevLayout) + 3) / 4);
 
+// Chunks [c0, cend) of one request, with the single-request bodies.
+__device__ __forceinline__ void run_tile(const DevLayout &L, const XferArgs &A, int unpack, int dense, int kind,
+                                         int64_t c0, int64_t cend, uint8_t *lds_dyn)
+{
+    if (dense) {
+        // sub-tiles sized to the type's LDS budget; LDS is reused between them
+        const int64_t st = L.rec.tile_chunks;
+        for (int64_t s0 = c0; s0 < cend; s0 += st) {
+            int64_t s1 = s0 + st < cend ? s0 + st : cend;
+            if (unpack) dense_unpack_tile(L, A, s0, s1, lds_dyn);
+            else dense_pack_tile(L, A, s0, s1, lds_dyn);
+            __syncthreads();
+        }
+        return;
+    }
+    for (int64_t s0 = c0; s0 < cend; s0 += 1024) {
+        int64_t s1 = s0 + 1024 < cend ? s0 + 1024 : cend;
+        if (unpack) {
+            if (kind == KIND_CONTIG) unpack_tile4<KIND_CONTIG>(L, A, s0, s1);
+            else if (kind == KIND_SINGLE) unpack_tile4<KIND_SINGLE>(L, A, s0, s1);
+            else unpack_tile4<KIND_MULTI>(L, A, s0, s1);
+        } else {
+            if (kind == KIND_CONTIG) pack_tile4<KIND_CONTIG>(L, A, s0, s1);
+            else if (kind == KIND_SINGLE) pack_tile4<KIND_SINGLE>(L, A, s0, s1);
+            else pack_tile4<KIND_MULTI>(L, A, s0, s1);
+        }
+    }
+}
+
 __global__ void batch_counter_reset(unsigned long long *counter) { *counter = 0ull; }
 
 // Persistent batch kernel.  POLICY 0: tile t = blockIdx.x + k * gridDim.x;
@@ -98,29 +127,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restric
         A.elem1 = D.elem1;
         int64_t c0 = (t - tile0[lo]) * T;
         int64_t cend = c0 + T < D.nchunks ? c0 + T : D.nchunks;
-        if (D.dense) {
-            // sub-tiles sized to the type's LDS budget; LDS is reused between them
-            const int64_t st = L.rec.tile_chunks;
-            for (int64_t s0 = c0; s0 < cend; s0 += st) {
-                int64_t s1 = s0 + st < cend ? s0 + st : cend;
-                if (D.unpack) dense_unpack_tile(L, A, s0, s1, lds_dyn);
-                else dense_pack_tile(L, A, s0, s1, lds_dyn);
-                __syncthreads();
-            }
-        } else {
-            for (int64_t s0 = c0; s0 < cend; s0 += 1024) {
-                int64_t s1 = s0 + 1024 < cend ? s0 + 1024 : cend;
-                if (D.unpack) {
-                    if (D.kind == KIND_CONTIG) unpack_tile4<KIND_CONTIG>(L, A, s0, s1);
-                    else if (D.kind == KIND_SINGLE) unpack_tile4<KIND_SINGLE>(L, A, s0, s1);
-                    else unpack_tile4<KIND_MULTI>(L, A, s0, s1);
-                } else {
-                    if (D.kind == KIND_CONTIG) pack_tile4<KIND_CONTIG>(L, A, s0, s1);
-                    else if (D.kind == KIND_SINGLE) pack_tile4<KIND_SINGLE>(L, A, s0, s1);
-                    else pack_tile4<KIND_MULTI>(L, A, s0, s1);
-                }
-            }
-        }
+        run_tile(L, A, D.unpack, D.dense, D.kind, c0, cend, lds_dyn);
         if (POLICY == 0) {
             t += gridDim.x;
         } else {

@@ -762,7 +762,7 @@ void lower_records(const Layout &L, Compiled &C)
     }
     if (hi - lo > 65535) return;
     // LDS for a tile: typed span (+ slack) + packed tile, and both tables
-    int tc = 512;
+    int tc = 2048;
     auto need = [&](int c) {
         int64_t nrec = (16 * (int64_t)c + U - 1) / U + 1;
         int64_t span = (nrec - 1) * X + (hi - lo) + 48;

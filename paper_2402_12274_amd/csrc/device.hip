@@ -152,14 +152,19 @@ int device_tables(Compiled *c, DeviceTables **out)
     return MDT_SUCCESS;
 }
 
+// Persistent grid: workgroup b takes tiles b, b + grid, ... so waves stay
+// resident and the per-workgroup prologue (descriptor loads) is amortised.
 template <int KIND, bool UNPACK>
 __global__ __launch_bounds__(256) void xfer_kernel(const DevLayout L, const XferArgs A)
 {
-    int64_t c0 = xcd_tile() * A.tile_chunks;
-    int64_t cend = c0 + A.tile_chunks < A.nchunks ? c0 + A.tile_chunks : A.nchunks;
-    // tile_chunks <= 1024: at most four chunks per lane
-    if (UNPACK) unpack_tile4<KIND>(L, A, c0, cend);
-    else pack_tile4<KIND>(L, A, c0, cend);
+    const int64_t ntiles = (A.nchunks + A.tile_chunks - 1) / A.tile_chunks;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int64_t c0 = t * A.tile_chunks;
+        int64_t cend = c0 + A.tile_chunks < A.nchunks ? c0 + A.tile_chunks : A.nchunks;
+        // tile_chunks <= 1024: at most four chunks per lane
+        if (UNPACK) unpack_tile4<KIND>(L, A, c0, cend);
+        else pack_tile4<KIND>(L, A, c0, cend);
+    }
 }
 
 // dense record streams: one tile of chunks per workgroup, staged in LDS
@@ -167,10 +172,14 @@ template <bool UNPACK>
 __global__ __launch_bounds__(256) void dense_kernel(const DevLayout L, const XferArgs A)
 {
     extern __shared__ __align__(16) uint8_t lds_dyn[];
-    int64_t c0 = xcd_tile() * A.tile_chunks;
-    int64_t c1 = c0 + A.tile_chunks < A.nchunks ? c0 + A.tile_chunks : A.nchunks;
-    if (UNPACK) dense_unpack_tile(L, A, c0, c1, lds_dyn);
-    else dense_pack_tile(L, A, c0, c1, lds_dyn);
+    const int64_t ntiles = (A.nchunks + A.tile_chunks - 1) / A.tile_chunks;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int64_t c0 = t * A.tile_chunks;
+        int64_t c1 = c0 + A.tile_chunks < A.nchunks ? c0 + A.tile_chunks : A.nchunks;
+        if (UNPACK) dense_unpack_tile(L, A, c0, c1, lds_dyn);
+        else dense_pack_tile(L, A, c0, c1, lds_dyn);
+        __syncthreads();  // LDS is reused by the next tile
+    }
 }
 
 // run tables: tile of chunks with the tile's groups cached in LDS
@@ -178,9 +187,13 @@ template <bool UNPACK>
 __global__ __launch_bounds__(256) void runs_kernel(const DevLayout L, const XferArgs A)
 {
     __shared__ RunsCache cache;
-    int64_t c0 = xcd_tile() * A.tile_chunks;
-    int64_t c1 = c0 + A.tile_chunks < A.nchunks ? c0 + A.tile_chunks : A.nchunks;
-    runs_tile<UNPACK>(L, A, c0, c1, cache);
+    const int64_t ntiles = (A.nchunks + A.tile_chunks - 1) / A.tile_chunks;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int64_t c0 = t * A.tile_chunks;
+        int64_t c1 = c0 + A.tile_chunks < A.nchunks ? c0 + A.tile_chunks : A.nchunks;
+        runs_tile<UNPACK>(L, A, c0, c1, cache);
+        __syncthreads();  // the cache is refilled for the next tile
+    }
 }
 
 // flatten: one lane per segment
@@ -206,6 +219,27 @@ __global__ __launch_bounds__(256) void flatten_table_kernel(const mdt_iov *segs,
 
 // ---------------------------------------------------------------------------
 // launch
+
+// Workgroups of a persistent launch: tiles, capped at `per_cu` resident
+// workgroups on every compute unit.
+static int64_t persistent_grid(int64_t ntiles, int per_cu)
+{
+    static const int ncu = [] {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+        return n;
+    }();
+    int64_t cap = (int64_t)ncu * per_cu;
+    return ntiles < cap ? ntiles : cap;
+}
+
+static int env_int(const char *name, int dflt)
+{
+    const char *e = getenv(name);
+    return e && *e ? atoi(e) : dflt;
+}
 
 int64_t default_tile_chunks(int64_t nchunks)
 {
@@ -246,8 +280,7 @@ int launch_xfer(const DevLayout &L, const XferArgs &A0, bool unpack, hipStream_t
     A.elem1 = A.off + A.nbytes <= L.size;
     if (use_dense(L, A, unpack)) {
         A.tile_chunks = L.rec.tile_chunks;
-        int64_t grid = (A.nchunks + A.tile_chunks - 1) / A.tile_chunks;
-        if (grid > 0x7fffffff) return MDT_ERR_ARG;
+        int64_t grid = persistent_grid((A.nchunks + A.tile_chunks - 1) / A.tile_chunks, env_int("MDT_WG_PER_CU", 8));
         size_t lds = (size_t)L.rec.lds_bytes;
         if (unpack) hipLaunchKernelGGL(dense_kernel<true>, dim3((unsigned)grid), dim3(256), lds, s, L, A);
         else hipLaunchKernelGGL(dense_kernel<false>, dim3((unsigned)grid), dim3(256), lds, s, L, A);
@@ -256,16 +289,14 @@ int launch_xfer(const DevLayout &L, const XferArgs &A0, bool unpack, hipStream_t
     }
     if (L.kind == KIND_MULTI && L.runs_only && runs_enabled()) {
         A.tile_chunks = 1024;
-        int64_t grid = (A.nchunks + A.tile_chunks - 1) / A.tile_chunks;
-        if (grid > 0x7fffffff) return MDT_ERR_ARG;
+        int64_t grid = persistent_grid((A.nchunks + A.tile_chunks - 1) / A.tile_chunks, env_int("MDT_WG_PER_CU", 8));
         if (unpack) hipLaunchKernelGGL(runs_kernel<true>, dim3((unsigned)grid), dim3(256), 0, s, L, A);
         else hipLaunchKernelGGL(runs_kernel<false>, dim3((unsigned)grid), dim3(256), 0, s, L, A);
         HIPCHK(hipGetLastError());
         return MDT_SUCCESS;
     }
     if (A.tile_chunks <= 0 || A.tile_chunks > 1024) A.tile_chunks = default_tile_chunks(A.nchunks);
-    int64_t grid = (A.nchunks + A.tile_chunks - 1) / A.tile_chunks;
-    if (grid > 0x7fffffff) return MDT_ERR_ARG;
+    int64_t grid = persistent_grid((A.nchunks + A.tile_chunks - 1) / A.tile_chunks, env_int("MDT_WG_PER_CU", 8));
     dim3 g((unsigned)grid), b(256);
 #define LAUNCH(K)                                                                    \
     do {                                                                             \

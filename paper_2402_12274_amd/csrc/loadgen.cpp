@@ -172,13 +172,15 @@ __attribute__((visibility("default"))) int mdt_lg_run_plain(const mdt_lg_req *re
         double t_arrive;
         int64_t bytes;
     };
-    std::deque<Pending> pend;
+    // requests on one stream complete in order: poll only each stream's oldest
+    std::vector<std::deque<Pending>> pend((size_t)nstreams);
+    int64_t npend = 0;
     std::vector<double> lat;
     lat.reserve((size_t)n);
     const double t0 = now_us() + 1000.0;
     double last_done = t0;
     int64_t i = 0;
-    while (i < n || !pend.empty()) {
+    while (i < n || npend > 0) {
         double t = now_us();
         while (i < n && t0 + reqs[i].t_arrive_us <= t) {
             const mdt_lg_req &q = reqs[i];
@@ -194,24 +196,26 @@ __attribute__((visibility("default"))) int mdt_lg_run_plain(const mdt_lg_req *re
             if (t - (t0 + q.t_arrive_us) > 50.0) res->late_issues++;
             if (e) res->failed++;
             else {
-                pend.push_back({r, t0 + q.t_arrive_us, got});
+                pend[(size_t)(i % nstreams)].push_back({r, t0 + q.t_arrive_us, got});
+                npend++;
                 res->launches++;
             }
             i++;
         }
-        size_t lim = std::min<size_t>(pend.size(), 4096);
-        for (size_t k = 0; k < lim; k++) {
-            if (!pend[k].r) continue;
-            int flag = 0;
-            mdt_test(&pend[k].r, &flag);
-            if (!flag) continue;
-            double tc = now_us();
-            res->completed++;
-            res->bytes += pend[k].bytes;
-            lat.push_back(tc - pend[k].t_arrive);
-            last_done = std::max(last_done, tc);
+        for (auto &dq : pend) {
+            while (!dq.empty()) {
+                int flag = 0;
+                mdt_test(&dq.front().r, &flag);
+                if (!flag) break;
+                double tc = now_us();
+                res->completed++;
+                res->bytes += dq.front().bytes;
+                lat.push_back(tc - dq.front().t_arrive);
+                last_done = std::max(last_done, tc);
+                dq.pop_front();
+                npend--;
+            }
         }
-        while (!pend.empty() && pend.front().r == nullptr) pend.pop_front();
         if (i < n && t0 + reqs[i].t_arrive_us > now_us() + 20.0) std::this_thread::sleep_for(std::chrono::microseconds(5));
     }
     for (int s = 0; s < nstreams; s++) {

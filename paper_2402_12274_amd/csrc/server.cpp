@@ -136,6 +136,7 @@ struct mdt_server_s {
     int inject_fail = 0;
     std::atomic<bool> run_thread{false};
     bool draining = false;       // shutdown: admit regardless of the budget
+    std::condition_variable wake;  // submit -> idle progress thread
     std::thread th;
     // stats
     int64_t submitted = 0, completed = 0, failed = 0, deferred = 0, bytes = 0, launches = 0;
@@ -280,6 +281,9 @@ int progress(mdt_server s)
     return progress_locked(s);
 }
 
+// The progress thread polls continuously while anything is queued,
+// admitted or in flight, and sleeps on a condition variable (woken by
+// submit) when the server is idle.
 void thread_main(mdt_server s)
 {
     (void)hipSetDevice(s->device);
@@ -293,8 +297,11 @@ void thread_main(mdt_server s)
             std::lock_guard<std::mutex> q(s->qmu);
             idle = !busy && s->queue.empty();
         }
-        if (idle) std::this_thread::sleep_for(std::chrono::microseconds(20));
-        else std::this_thread::yield();
+        if (idle) {
+            std::unique_lock<std::mutex> q(s->qmu);
+            s->wake.wait_for(q, std::chrono::milliseconds(1),
+                             [s] { return !s->queue.empty() || !s->run_thread.load(std::memory_order_acquire); });
+        }
     }
 }
 
@@ -328,6 +335,7 @@ int submit(mdt_server s, Item *it, mdt_request *req)
         std::lock_guard<std::mutex> q(s->qmu);
         s->queue.push_back(it);
     }
+    s->wake.notify_one();
     *req = r;
     return MDT_SUCCESS;
 }
@@ -549,6 +557,7 @@ MDT_API int mdt_server_stop_progress_thread(mdt_server srv)
 {
     if (!valid_server(srv)) return MDT_ERR_ARG;
     if (!srv->run_thread.exchange(false)) return MDT_SUCCESS;
+    srv->wake.notify_all();
     if (srv->th.joinable()) srv->th.join();
     return MDT_SUCCESS;
 }

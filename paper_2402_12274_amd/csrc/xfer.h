@@ -268,14 +268,7 @@ __device__ __forceinline__ void unpack_tile4(const DevLayout &L, const XferArgs 
     }
 }
 
-// tile index of this workgroup: the grid is dealt round-robin over the 8
-// XCDs, so give XCD x the x-th contiguous share of the tiles
-__device__ __forceinline__ int64_t xcd_tile()
-{
-    int64_t nb = gridDim.x, b = blockIdx.x;
-    int64_t q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
-    return x * q + (x < r ? x : r) + i;
-}
+
 
 }  // namespace mdt
 

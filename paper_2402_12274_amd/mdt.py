@@ -168,10 +168,13 @@ class Type:
         self.owned = owned
 
     def __del__(self):
-        if getattr(self, "owned", False) and self.handle:
-            h = _P(self.handle)
-            _lib.mdt_type_free(C.byref(h))
-            self.handle = None
+        try:
+            if getattr(self, "owned", False) and self.handle:
+                h = _P(self.handle)
+                _lib.mdt_type_free(C.byref(h))
+                self.handle = None
+        except Exception:  # interpreter shutdown: module globals may be gone
+            pass
 
     @property
     def h(self):
@@ -308,8 +311,11 @@ class Stream:
         check(_lib.mdt_stream_create(_P(hip_stream), C.byref(self.handle)), "stream_create")
 
     def __del__(self):
-        if getattr(self, "handle", None) and self.handle.value:
-            _lib.mdt_stream_free(C.byref(self.handle))
+        try:
+            if getattr(self, "handle", None) and self.handle.value:
+                _lib.mdt_stream_free(C.byref(self.handle))
+        except Exception:
+            pass
 
     @property
     def h(self):
@@ -369,8 +375,11 @@ class Batch:
         self._keep = []
 
     def __del__(self):
-        if getattr(self, "handle", None) and self.handle.value:
-            _lib.mdt_batch_free(C.byref(self.handle))
+        try:
+            if getattr(self, "handle", None) and self.handle.value:
+                _lib.mdt_batch_free(C.byref(self.handle))
+        except Exception:
+            pass
 
     def clear(self):
         check(_lib.mdt_batch_clear(self.handle), "batch_clear")
