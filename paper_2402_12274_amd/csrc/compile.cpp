@@ -17,6 +17,7 @@
 // case), run number k is segment number k and both queries are answered by
 // position arithmetic; otherwise a merged segment table is built once.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
@@ -762,7 +763,12 @@ void lower_records(const Layout &L, Compiled &C)
     }
     if (hi - lo > 65535) return;
     // LDS for a tile: typed span (+ slack) + packed tile, and both tables
-    int tc = 2048;
+    static const int tc_max = [] {
+        const char *e = getenv("MDT_DENSE_TILE");
+        int v = e && *e ? atoi(e) : 2048;
+        return v >= 64 && v <= 2048 ? v : 2048;
+    }();
+    int tc = tc_max;
     auto need = [&](int c) {
         int64_t nrec = (16 * (int64_t)c + U - 1) / U + 1;
         int64_t span = (nrec - 1) * X + (hi - lo) + 48;

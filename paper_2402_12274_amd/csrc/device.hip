@@ -152,8 +152,7 @@ int device_tables(Compiled *c, DeviceTables **out)
     return MDT_SUCCESS;
 }
 
-// Persistent grid: workgroup b takes tiles b, b + grid, ... so waves stay
-// resident and the per-workgroup prologue (descriptor loads) is amortised.
+// Workgroup b takes tiles b, b + grid, ... (normally grid = tiles).
 template <int KIND, bool UNPACK>
 __global__ __launch_bounds__(256) void xfer_kernel(const DevLayout L, const XferArgs A)
 {
@@ -220,25 +219,22 @@ __global__ __launch_bounds__(256) void flatten_table_kernel(const mdt_iov *segs,
 // ---------------------------------------------------------------------------
 // launch
 
-// Workgroups of a persistent launch: tiles, capped at `per_cu` resident
-// workgroups on every compute unit.
-static int64_t persistent_grid(int64_t ntiles, int per_cu)
+// Workgroups of a launch: one per tile by default (measured faster than a
+// grid capped at the resident capacity, whose second round of workgroups
+// runs as a serialized tail); MDT_WG_PER_CU > 0 caps it for experiments.
+static int64_t launch_grid(int64_t ntiles)
 {
-    static const int ncu = [] {
+    static const int64_t cap = [] {
+        const char *e = getenv("MDT_WG_PER_CU");
+        int per_cu = e && *e ? atoi(e) : 0;
+        if (per_cu <= 0) return (int64_t)0;
         int dev = 0, n = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
             n = 256;
-        return n;
+        return (int64_t)n * per_cu;
     }();
-    int64_t cap = (int64_t)ncu * per_cu;
-    return ntiles < cap ? ntiles : cap;
-}
-
-static int env_int(const char *name, int dflt)
-{
-    const char *e = getenv(name);
-    return e && *e ? atoi(e) : dflt;
+    return cap > 0 && ntiles > cap ? cap : ntiles;
 }
 
 int64_t default_tile_chunks(int64_t nchunks)
@@ -280,7 +276,7 @@ int launch_xfer(const DevLayout &L, const XferArgs &A0, bool unpack, hipStream_t
     A.elem1 = A.off + A.nbytes <= L.size;
     if (use_dense(L, A, unpack)) {
         A.tile_chunks = L.rec.tile_chunks;
-        int64_t grid = persistent_grid((A.nchunks + A.tile_chunks - 1) / A.tile_chunks, env_int("MDT_WG_PER_CU", 8));
+        int64_t grid = launch_grid((A.nchunks + A.tile_chunks - 1) / A.tile_chunks);
         size_t lds = (size_t)L.rec.lds_bytes;
         if (unpack) hipLaunchKernelGGL(dense_kernel<true>, dim3((unsigned)grid), dim3(256), lds, s, L, A);
         else hipLaunchKernelGGL(dense_kernel<false>, dim3((unsigned)grid), dim3(256), lds, s, L, A);
@@ -289,14 +285,14 @@ int launch_xfer(const DevLayout &L, const XferArgs &A0, bool unpack, hipStream_t
     }
     if (L.kind == KIND_MULTI && L.runs_only && runs_enabled()) {
         A.tile_chunks = 1024;
-        int64_t grid = persistent_grid((A.nchunks + A.tile_chunks - 1) / A.tile_chunks, env_int("MDT_WG_PER_CU", 8));
+        int64_t grid = launch_grid((A.nchunks + A.tile_chunks - 1) / A.tile_chunks);
         if (unpack) hipLaunchKernelGGL(runs_kernel<true>, dim3((unsigned)grid), dim3(256), 0, s, L, A);
         else hipLaunchKernelGGL(runs_kernel<false>, dim3((unsigned)grid), dim3(256), 0, s, L, A);
         HIPCHK(hipGetLastError());
         return MDT_SUCCESS;
     }
     if (A.tile_chunks <= 0 || A.tile_chunks > 1024) A.tile_chunks = default_tile_chunks(A.nchunks);
-    int64_t grid = persistent_grid((A.nchunks + A.tile_chunks - 1) / A.tile_chunks, env_int("MDT_WG_PER_CU", 8));
+    int64_t grid = launch_grid((A.nchunks + A.tile_chunks - 1) / A.tile_chunks);
     dim3 g((unsigned)grid), b(256);
 #define LAUNCH(K)                                                                    \
     do {                                                                             \

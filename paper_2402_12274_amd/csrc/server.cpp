@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstdlib>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -46,6 +47,17 @@ namespace {
 
 constexpr uint32_t SERVER_MAGIC = 0x6d647356u;
 constexpr int64_t ARENA_ALIGN = 256;
+// A launch stops taking requests once it holds this many bytes, so small
+// requests are not held back by a large one in the same launch (a large
+// request still goes alone).
+const int64_t BATCH_BYTES = [] {
+    const char *e = getenv("MDT_SERVER_BATCH_BYTES");
+    long long v = e && *e ? atoll(e) : (8ll << 20);
+    return (int64_t)(v > 0 ? v : (8ll << 20));
+}();
+// The progress thread keeps polling for this long after the last activity
+// before it sleeps (a sleeping thread wakes with scheduler latency).
+constexpr double SPIN_US = 2000.0;
 
 double now_us()
 {
@@ -241,8 +253,11 @@ int progress_locked(mdt_server s)
             }
         mdt_batch_clear(sl->batch);
         int n = 0;
+        int64_t bytes = 0;
         while (!s->admitted.empty() && n < s->cfg.max_batch) {
             Item *it = s->admitted.front();
+            if (n > 0 && bytes + it->nbytes > BATCH_BYTES) break;
+            bytes += it->nbytes;
             s->admitted.pop_front();
             int64_t got = 0;
             int r;
@@ -287,6 +302,7 @@ int progress(mdt_server s)
 void thread_main(mdt_server s)
 {
     (void)hipSetDevice(s->device);
+    double last_active = now_us();
     while (s->run_thread.load(std::memory_order_acquire)) {
         bool idle;
         {
@@ -297,7 +313,13 @@ void thread_main(mdt_server s)
             std::lock_guard<std::mutex> q(s->qmu);
             idle = !busy && s->queue.empty();
         }
-        if (idle) {
+        double t = now_us();
+        if (!idle) last_active = t;
+        if (!idle || t - last_active < SPIN_US) {
+            std::this_thread::yield();
+            continue;
+        }
+        {
             std::unique_lock<std::mutex> q(s->qmu);
             s->wake.wait_for(q, std::chrono::milliseconds(1),
                              [s] { return !s->queue.empty() || !s->run_thread.load(std::memory_order_acquire); });
@@ -336,6 +358,12 @@ int submit(mdt_server s, Item *it, mdt_request *req)
         s->queue.push_back(it);
     }
     s->wake.notify_one();
+    // dispatch right away when no progress round is running (light load);
+    // otherwise the running round or the progress thread picks it up
+    if (s->mu.try_lock()) {
+        progress_locked(s);
+        s->mu.unlock();
+    }
     *req = r;
     return MDT_SUCCESS;
 }
