@@ -765,8 +765,8 @@ void lower_records(const Layout &L, Compiled &C)
     // LDS for a tile: typed span (+ slack) + packed tile, and both tables
     static const int tc_max = [] {
         const char *e = getenv("MDT_DENSE_TILE");
-        int v = e && *e ? atoi(e) : 2048;
-        return v >= 64 && v <= 2048 ? v : 2048;
+        int v = e && *e ? atoi(e) : 1024;
+        return v >= 64 && v <= 2048 ? v : 1024;
     }();
     int tc = tc_max;
     auto need = [&](int c) {

@@ -39,6 +39,10 @@
 
 namespace mdt {
 int batch_launch_internal(mdt_batch b, hipStream_t s);
+int pack_common(const void *inbuf, int64_t incount, mdt_type t, int64_t inoffset, void *outbuf, int64_t max_bytes,
+                int64_t *actual, hipStream_t s, mdt_request *req);
+int unpack_common(const void *inbuf, int64_t insize, void *outbuf, int64_t outcount, mdt_type t, int64_t outoffset,
+                  int64_t *actual, hipStream_t s, mdt_request *req);
 }
 
 using namespace mdt;
@@ -251,6 +255,37 @@ int progress_locked(mdt_server s)
                 sl = &x;
                 break;
             }
+        // a lone request is launched with the single-request kernels (no
+        // descriptor upload); several go through one batched launch
+        size_t take_n = 0;
+        {
+            int64_t b = 0;
+            for (Item *it : s->admitted) {
+                if (take_n >= (size_t)s->cfg.max_batch || (take_n > 0 && b + it->nbytes > BATCH_BYTES)) break;
+                b += it->nbytes;
+                take_n++;
+            }
+        }
+        if (take_n == 1) {
+            Item *it = s->admitted.front();
+            s->admitted.pop_front();
+            int64_t got = 0;
+            mdt_type th = reinterpret_cast<mdt_type>(it->type);
+            int r = it->unpack ? unpack_common(it->in, it->nbytes, it->out, it->count, th, it->off, &got, best->s, nullptr)
+                               : pack_common(it->in, it->count, th, it->off, it->out, it->nbytes, &got, best->s, nullptr);
+            hipError_t e = r == MDT_SUCCESS ? hipEventRecord(sl->ev, best->s) : hipErrorUnknown;
+            if (r != MDT_SUCCESS || e != hipSuccess) {
+                complete(s, it, r ? r : MDT_ERR_HIP, now_us());
+                rc = r ? r : MDT_ERR_HIP;
+                continue;
+            }
+            it->state.store(2, std::memory_order_release);
+            sl->items.push_back(it);
+            sl->busy = true;
+            best->busy++;
+            s->launches++;
+            continue;
+        }
         mdt_batch_clear(sl->batch);
         int n = 0;
         int64_t bytes = 0;
