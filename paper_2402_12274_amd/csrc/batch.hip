@@ -47,7 +47,7 @@ struct BatchHeader {
 constexpr int LAY_WORDS = (int)((sizeof(DevLayout) + 3) / 4);
 
 // Chunks [c0, cend) of one request, with the single-request bodies.
-__device__ __forceinline__ void run_tile(const DevLayout &L, const XferArgs &A, int unpack, int dense, int kind,
+__device__ __forceinline__ void run_tile(const DevLayout &L, const XferArgs &A, const int unpack, int dense, int kind,
                                          int64_t c0, int64_t cend, uint8_t *lds_dyn)
 {
     if (dense) {
@@ -80,8 +80,8 @@ __global__ void batch_counter_reset(unsigned long long *counter) { *counter = 0u
 // Persistent batch kernel.  POLICY 0: tile t = blockIdx.x + k * gridDim.x;
 // POLICY 1: tiles taken from an atomic counter.  Every workgroup leaves the
 // loop once the tile index reaches ntiles.
-template <int POLICY>
-__global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restrict__ H,
+template <int POLICY, int UNPACK>
+__global__ __launch_bounds__(256, UNPACK ? 4 : 3) void batch_kernel(const BatchHeader *__restrict__ H,
                                                     const ReqDesc *__restrict__ R,
                                                     const int64_t *__restrict__ tile0,
                                                     unsigned long long *counter)
@@ -107,6 +107,18 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restric
             if (tile0[mid] <= t) lo = mid; else hi = mid - 1;
         }
         const ReqDesc D = R[lo];
+        if (D.unpack != UNPACK) {
+            // tile of the other direction: its own launch handles it
+            if (POLICY == 0) {
+                t += gridDim.x;
+            } else {
+                __syncthreads();
+                if (threadIdx.x == 0) s_t = (int64_t)atomicAdd(counter, 1ull);
+                __syncthreads();
+                t = s_t;
+            }
+            continue;
+        }
         if (lo != cur) {
             // stage the request's layout program in LDS (read by every lane)
             __syncthreads();
@@ -127,7 +139,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restric
         A.elem1 = D.elem1;
         int64_t c0 = (t - tile0[lo]) * T;
         int64_t cend = c0 + T < D.nchunks ? c0 + T : D.nchunks;
-        run_tile(L, A, D.unpack, D.dense, D.kind, c0, cend, lds_dyn);
+        run_tile(L, A, UNPACK, D.dense, D.kind, c0, cend, lds_dyn);
         if (POLICY == 0) {
             t += gridDim.x;
         } else {
@@ -166,6 +178,7 @@ struct mdt_batch_s {
     unsigned long long *d_counter = nullptr;
     int64_t ntiles = 0;
     int32_t lds = 0;  // dynamic LDS of the persistent kernel (largest dense request)
+    int32_t dirs = 0; // bit 0: has pack requests, bit 1: has unpack requests
     // captured launch
     hipGraphExec_t exec = nullptr;
     hipStream_t cap_stream = nullptr;
@@ -253,9 +266,11 @@ int stage(mdt_batch_s *b, hipStream_t s)
     int64_t *tile0 = (int64_t *)(b->h_stage + tile_off(b->cap));
     int64_t acc = 0;
     b->lds = 0;
+    b->dirs = 0;
     for (size_t i = 0; i < b->reqs.size(); i++) {
         D[i] = b->reqs[i].d;
         if (D[i].dense) b->lds = std::max(b->lds, b->reqs[i].lds);
+        b->dirs |= D[i].unpack ? 2 : 1;
         tile0[i] = acc;
         acc += (b->reqs[i].d.nchunks + T - 1) / T;
     }
@@ -286,11 +301,18 @@ void enqueue_kernels(mdt_batch_s *b, hipStream_t s, int grid)
     const BatchHeader *H = (const BatchHeader *)b->d_buf;
     const ReqDesc *R = (const ReqDesc *)(b->d_buf + desc_off());
     const int64_t *tile0 = (const int64_t *)(b->d_buf + tile_off(b->cap));
-    if (b->cfg.policy == 1) {
-        hipLaunchKernelGGL(batch_counter_reset, dim3(1), dim3(1), 0, s, b->d_counter);
-        hipLaunchKernelGGL(batch_kernel<1>, dim3(grid), dim3(256), (size_t)b->lds, s, H, R, tile0, b->d_counter);
-    } else {
-        hipLaunchKernelGGL(batch_kernel<0>, dim3(grid), dim3(256), (size_t)b->lds, s, H, R, tile0, b->d_counter);
+    // one kernel per direction: a mixed batch runs its pack tiles and its
+    // unpack tiles as two launches (each kernel skips the other direction)
+    for (int dir = 0; dir < 2; dir++) {
+        if (!(b->dirs & (1 << dir))) continue;
+        if (b->cfg.policy == 1) {
+            hipLaunchKernelGGL(batch_counter_reset, dim3(1), dim3(1), 0, s, b->d_counter);
+            if (dir) hipLaunchKernelGGL((batch_kernel<1, 1>), dim3(grid), dim3(256), (size_t)b->lds, s, H, R, tile0, b->d_counter);
+            else hipLaunchKernelGGL((batch_kernel<1, 0>), dim3(grid), dim3(256), (size_t)b->lds, s, H, R, tile0, b->d_counter);
+        } else {
+            if (dir) hipLaunchKernelGGL((batch_kernel<0, 1>), dim3(grid), dim3(256), (size_t)b->lds, s, H, R, tile0, b->d_counter);
+            else hipLaunchKernelGGL((batch_kernel<0, 0>), dim3(grid), dim3(256), (size_t)b->lds, s, H, R, tile0, b->d_counter);
+        }
     }
 }
 

@@ -128,12 +128,14 @@ struct Slot {
     hipEvent_t ev = nullptr;
     std::vector<Item *> items;
     bool busy = false;
+    uint64_t seq = 0;  // launch order on its stream
 };
 
 struct StreamState {
     hipStream_t s = nullptr;
     std::vector<Slot> slots;
     int busy = 0;
+    uint64_t next_seq = 0;
 };
 
 }  // namespace
@@ -183,12 +185,17 @@ void complete(mdt_server s, Item *it, int status, double t)
 int progress_locked(mdt_server s)
 {
     int rc = MDT_SUCCESS;
-    // 1. reap completed launches
+    // 1. reap completed launches; a stream finishes its launches in order, so
+    // only its oldest running launch is queried
     for (auto &st : s->streams) {
-        for (auto &sl : st.slots) {
-            if (!sl.busy) continue;
+        for (;;) {
+            Slot *old = nullptr;
+            for (auto &x : st.slots)
+                if (x.busy && (!old || x.seq < old->seq)) old = &x;
+            if (!old) break;
+            Slot &sl = *old;
             hipError_t e = hipEventQuery(sl.ev);
-            if (e == hipErrorNotReady) continue;
+            if (e == hipErrorNotReady) break;
             double t = now_us();
             int status = e == hipSuccess ? MDT_SUCCESS : MDT_ERR_HIP;
             if (e != hipSuccess) set_hip_error((int)e);
@@ -282,6 +289,7 @@ int progress_locked(mdt_server s)
             it->state.store(2, std::memory_order_release);
             sl->items.push_back(it);
             sl->busy = true;
+            sl->seq = best->next_seq++;
             best->busy++;
             s->launches++;
             continue;
@@ -319,6 +327,7 @@ int progress_locked(mdt_server s)
             continue;
         }
         sl->busy = true;
+        sl->seq = best->next_seq++;
         best->busy++;
         s->launches++;
     }
