@@ -168,7 +168,8 @@ def serve_bench(args, torch, mdt):
     class Res(C.Structure):
         _fields_ = [("completed", C.c_int64), ("failed", C.c_int64), ("bytes", C.c_int64), ("elapsed_s", C.c_double),
                     ("p50_us", C.c_double), ("p99_us", C.c_double), ("max_us", C.c_double), ("mean_us", C.c_double),
-                    ("launches", C.c_int64), ("late_issues", C.c_int64)]
+                    ("launches", C.c_int64), ("late_issues", C.c_int64), ("p50_queue_us", C.c_double),
+                    ("p99_queue_us", C.c_double), ("p50_run_us", C.c_double), ("p99_run_us", C.c_double)]
 
     size = np.array([t.size() for t in types], np.int64)
     ext = np.array([t.extent()[1] for t in types], np.int64)
@@ -213,7 +214,9 @@ def serve_bench(args, torch, mdt):
     def summ(r):
         return {"completed": r.completed, "failed": r.failed, "GBps": round(2 * r.bytes / r.elapsed_s / 1e9, 2),
                 "p50_us": round(r.p50_us, 1), "p99_us": round(r.p99_us, 1), "max_us": round(r.max_us, 1),
-                "launches": r.launches, "late_issues": r.late_issues, "elapsed_s": round(r.elapsed_s, 3)}
+                "launches": r.launches, "late_issues": r.late_issues, "elapsed_s": round(r.elapsed_s, 3),
+                "server_p50_queue_us": round(r.p50_queue_us, 1), "server_p99_queue_us": round(r.p99_queue_us, 1),
+                "server_p50_run_us": round(r.p50_run_us, 1), "server_p99_run_us": round(r.p99_run_us, 1)}
 
     s_, p_ = summ(served), summ(plain)
     out = {

@@ -289,6 +289,8 @@ typedef struct mdt_server_stats {
     double p50_us, p99_us, max_us; /* latency: completion seen by host - submission */
     double elapsed_s;          /* first submission to last completion */
     mdt_count inflight_bytes, peak_inflight_bytes;
+    double p50_queue_us, p99_queue_us; /* submission -> launch */
+    double p50_run_us, p99_run_us;     /* launch -> completion seen by the progress engine */
 } mdt_server_stats;
 MDT_API int mdt_server_create(const mdt_server_config *cfg, mdt_server *out);
 /* Drains every admitted request, stops the progress thread, frees the

@@ -44,6 +44,7 @@ struct mdt_lg_result {
     double p50_us, p99_us, max_us, mean_us;
     int64_t launches;
     int64_t late_issues;  // requests issued more than 50 us after their scheduled time
+    double p50_queue_us, p99_queue_us, p50_run_us, p99_run_us;  // served: server-side split
 };
 
 }  // extern "C"
@@ -150,6 +151,10 @@ __attribute__((visibility("default"))) int mdt_lg_run_served(const mdt_lg_req *r
     mdt_server_stats st{};
     mdt_server_stats_get(srv, &st);
     res->launches = st.launches;
+    res->p50_queue_us = st.p50_queue_us;
+    res->p99_queue_us = st.p99_queue_us;
+    res->p50_run_us = st.p50_run_us;
+    res->p99_run_us = st.p99_run_us;
     mdt_server_free(&srv);
     res->elapsed_s = (last_done - t0) * 1e-6;
     summarize(lat, res);

@@ -79,7 +79,7 @@ struct Item {
     int64_t arena_off = -1;
     void *packed = nullptr;
     int status = MDT_SUCCESS;
-    double t_submit = 0, t_done = 0;
+    double t_submit = 0, t_launch = 0, t_done = 0;
     std::atomic<int> state{0};  // 0 queued, 1 admitted, 2 launched, 3 done
     bool deferred = false;
 };
@@ -154,12 +154,13 @@ struct mdt_server_s {
     int inject_fail = 0;
     std::atomic<bool> run_thread{false};
     bool draining = false;       // shutdown: admit regardless of the budget
+    std::atomic<bool> light{true};  // few launches in flight: submitters may dispatch
     std::condition_variable wake;  // submit -> idle progress thread
     std::thread th;
     // stats
     int64_t submitted = 0, completed = 0, failed = 0, deferred = 0, bytes = 0, launches = 0;
     double first_submit = -1, last_done = 0;
-    std::vector<float> lat_us;
+    std::vector<float> lat_us, queue_us, run_us;
 };
 
 namespace {
@@ -174,6 +175,10 @@ void complete(mdt_server s, Item *it, int status, double t)
         s->completed++;
         s->bytes += it->nbytes;
         s->lat_us.push_back((float)(t - it->t_submit));
+        if (it->t_launch > 0) {
+            s->queue_us.push_back((float)(it->t_launch - it->t_submit));
+            s->run_us.push_back((float)(t - it->t_launch));
+        }
     } else {
         s->failed++;
     }
@@ -287,6 +292,7 @@ int progress_locked(mdt_server s)
                 continue;
             }
             it->state.store(2, std::memory_order_release);
+            it->t_launch = now_us();
             sl->items.push_back(it);
             sl->busy = true;
             sl->seq = best->next_seq++;
@@ -319,6 +325,10 @@ int progress_locked(mdt_server s)
         }
         if (sl->items.empty()) continue;
         int r = batch_launch_internal(sl->batch, best->s);
+        {
+            double tl = now_us();
+            for (Item *it : sl->items) it->t_launch = tl;
+        }
         hipError_t e = r == MDT_SUCCESS ? hipEventRecord(sl->ev, best->s) : hipErrorUnknown;
         if (r != MDT_SUCCESS || e != hipSuccess) {
             for (Item *it : sl->items) complete(s, it, r ? r : MDT_ERR_HIP, now_us());
@@ -331,6 +341,9 @@ int progress_locked(mdt_server s)
         best->busy++;
         s->launches++;
     }
+    int inflight = 0;
+    for (auto &st : s->streams) inflight += st.busy;
+    s->light.store(inflight < (int)s->streams.size() && s->admitted.empty(), std::memory_order_relaxed);
     return rc;
 }
 
@@ -402,9 +415,9 @@ int submit(mdt_server s, Item *it, mdt_request *req)
         s->queue.push_back(it);
     }
     s->wake.notify_one();
-    // dispatch right away when no progress round is running (light load);
-    // otherwise the running round or the progress thread picks it up
-    if (s->mu.try_lock()) {
+    // light load: dispatch right away when no progress round is running and
+    // nothing else waits; under load the progress thread batches instead
+    if (s->light.load(std::memory_order_relaxed) && s->mu.try_lock()) {
         progress_locked(s);
         s->mu.unlock();
     }
@@ -648,18 +661,22 @@ MDT_API int mdt_server_stats_get(mdt_server srv, mdt_server_stats *out)
     out->peak_inflight_bytes = srv->peak_inflight;
     out->elapsed_s = srv->first_submit >= 0 ? (srv->last_done - srv->first_submit) * 1e-6 : 0.0;
     out->p50_us = out->p99_us = out->max_us = 0;
-    if (!srv->lat_us.empty()) {
-        std::vector<float> v = srv->lat_us;
+    auto pct = [](std::vector<float> v, double f) {
+        if (v.empty()) return 0.0;
         size_t n = v.size();
-        auto q = [&](double f) {
-            size_t k = std::min(n - 1, (size_t)(f * (double)(n - 1) + 0.5));
-            std::nth_element(v.begin(), v.begin() + k, v.end());
-            return (double)v[k];
-        };
-        out->p50_us = q(0.50);
-        out->p99_us = q(0.99);
-        out->max_us = *std::max_element(v.begin(), v.end());
+        size_t k = std::min(n - 1, (size_t)(f * (double)(n - 1) + 0.5));
+        std::nth_element(v.begin(), v.begin() + k, v.end());
+        return (double)v[k];
+    };
+    if (!srv->lat_us.empty()) {
+        out->p50_us = pct(srv->lat_us, 0.50);
+        out->p99_us = pct(srv->lat_us, 0.99);
+        out->max_us = *std::max_element(srv->lat_us.begin(), srv->lat_us.end());
     }
+    out->p50_queue_us = pct(srv->queue_us, 0.50);
+    out->p99_queue_us = pct(srv->queue_us, 0.99);
+    out->p50_run_us = pct(srv->run_us, 0.50);
+    out->p99_run_us = pct(srv->run_us, 0.99);
     return MDT_SUCCESS;
 }
 

@@ -64,7 +64,9 @@ class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
                 ("deferred", C.c_int64), ("bytes", C.c_int64), ("launches", C.c_int64),
                 ("p50_us", C.c_double), ("p99_us", C.c_double), ("max_us", C.c_double),
-                ("elapsed_s", C.c_double), ("inflight_bytes", C.c_int64), ("peak_inflight_bytes", C.c_int64)]
+                ("elapsed_s", C.c_double), ("inflight_bytes", C.c_int64), ("peak_inflight_bytes", C.c_int64),
+                ("p50_queue_us", C.c_double), ("p99_queue_us", C.c_double), ("p50_run_us", C.c_double),
+                ("p99_run_us", C.c_double)]
 
 
 _SIGS = {
