@@ -29,7 +29,7 @@
 namespace mdt {
 
 struct ReqDesc {
-    const DevLayout *lay;  // device copy of the request's layout program
+    uint64_t lay;          // address of the device copy of the request's layout program
     const uint8_t *typed;
     uint8_t *packed;
     int64_t off, nbytes, head, nchunks;
@@ -43,8 +43,6 @@ struct BatchHeader {
     int64_t tile_chunks;
     int64_t pad;
 };
-
-constexpr int LAY_WORDS = (int)((sizeof(DevLayout) + 3) / 4);
 
 // Chunks [c0, cend) of one request, with the single-request bodies.
 __device__ __forceinline__ void run_tile(const DevLayout &L, const XferArgs &A, const int unpack, int dense, int kind,
@@ -77,27 +75,43 @@ __device__ __forceinline__ void run_tile(const DevLayout &L, const XferArgs &A, 
 
 __global__ void batch_counter_reset(unsigned long long *counter) { *counter = 0ull; }
 
+// The same value in every lane, as a scalar (the tile index a workgroup
+// works on is uniform; saying so keeps the request lookup and the layout
+// reads on the scalar unit).
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// A layout program read through the constant address space: it does not
+// change while a kernel runs, so uniform reads of it become scalar loads, as
+// they are for a layout passed by value as a kernel argument.
+__device__ __forceinline__ const DevLayout &const_layout(uint64_t addr)
+{
+    return *(const DevLayout *)(const __attribute__((address_space(4))) DevLayout *)(uintptr_t)addr;
+}
+
 // Persistent batch kernel.  POLICY 0: tile t = blockIdx.x + k * gridDim.x;
 // POLICY 1: tiles taken from an atomic counter.  Every workgroup leaves the
 // loop once the tile index reaches ntiles.
 template <int POLICY, int UNPACK>
-__global__ __launch_bounds__(256, UNPACK ? 4 : 3) void batch_kernel(const BatchHeader *__restrict__ H,
+__global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restrict__ H,
                                                     const ReqDesc *__restrict__ R,
                                                     const int64_t *__restrict__ tile0,
                                                     unsigned long long *counter)
 {
-    __shared__ __align__(16) uint32_t s_lay[LAY_WORDS];
     extern __shared__ __align__(16) uint8_t lds_dyn[];
     __shared__ int64_t s_t;
     const int64_t ntiles = H->ntiles, T = H->tile_chunks, nreq = H->nreq;
-    int64_t cur = -1;
     int64_t t;
     if (POLICY == 0) {
         t = blockIdx.x;
     } else {
         if (threadIdx.x == 0) s_t = (int64_t)atomicAdd(counter, 1ull);
         __syncthreads();
-        t = s_t;
+        t = uniform64(s_t);
     }
     while (t < ntiles) {
         // request holding tile t: last r with tile0[r] <= t
@@ -106,47 +120,29 @@ __global__ __launch_bounds__(256, UNPACK ? 4 : 3) void batch_kernel(const BatchH
             int64_t mid = (lo + hi + 1) >> 1;
             if (tile0[mid] <= t) lo = mid; else hi = mid - 1;
         }
-        const ReqDesc D = R[lo];
-        if (D.unpack != UNPACK) {
-            // tile of the other direction: its own launch handles it
-            if (POLICY == 0) {
-                t += gridDim.x;
-            } else {
-                __syncthreads();
-                if (threadIdx.x == 0) s_t = (int64_t)atomicAdd(counter, 1ull);
-                __syncthreads();
-                t = s_t;
-            }
-            continue;
+        const ReqDesc &D = R[lo];
+        if (D.unpack == UNPACK) {  // tiles of the other direction belong to its own launch
+            const DevLayout &L = const_layout(D.lay);
+            XferArgs A;
+            A.typed = D.typed;
+            A.packed = D.packed;
+            A.off = D.off;
+            A.nbytes = D.nbytes;
+            A.head = D.head;
+            A.nchunks = D.nchunks;
+            A.tile_chunks = T;
+            A.elem1 = D.elem1;
+            int64_t c0 = (t - tile0[lo]) * T;
+            int64_t cend = c0 + T < D.nchunks ? c0 + T : D.nchunks;
+            run_tile(L, A, UNPACK, D.dense, D.kind, c0, cend, lds_dyn);
         }
-        if (lo != cur) {
-            // stage the request's layout program in LDS (read by every lane)
-            __syncthreads();
-            const uint32_t *src = (const uint32_t *)D.lay;
-            for (int i = threadIdx.x; i < LAY_WORDS; i += 256) s_lay[i] = src[i];
-            __syncthreads();
-            cur = lo;
-        }
-        const DevLayout &L = *(const DevLayout *)s_lay;
-        XferArgs A;
-        A.typed = D.typed;
-        A.packed = D.packed;
-        A.off = D.off;
-        A.nbytes = D.nbytes;
-        A.head = D.head;
-        A.nchunks = D.nchunks;
-        A.tile_chunks = T;
-        A.elem1 = D.elem1;
-        int64_t c0 = (t - tile0[lo]) * T;
-        int64_t cend = c0 + T < D.nchunks ? c0 + T : D.nchunks;
-        run_tile(L, A, UNPACK, D.dense, D.kind, c0, cend, lds_dyn);
         if (POLICY == 0) {
             t += gridDim.x;
         } else {
             __syncthreads();
             if (threadIdx.x == 0) s_t = (int64_t)atomicAdd(counter, 1ull);
             __syncthreads();
-            t = s_t;
+            t = uniform64(s_t);
         }
     }
 }
@@ -446,7 +442,7 @@ MDT_API int mdt_batch_add_pack(mdt_batch b, const void *inbuf, mdt_count incount
         XferArgs A = make_args(inbuf, outbuf, inoffset, n);
         A.elem1 = A.off + A.nbytes <= D->lay.size;
         int dense = use_dense(D->lay, A, false);
-        ReqDesc d{D->d_lay, A.typed, A.packed, A.off, A.nbytes, A.head, A.nchunks, 0, D->lay.kind, A.elem1, dense};
+        ReqDesc d{(uint64_t)(uintptr_t)D->d_lay, A.typed, A.packed, A.off, A.nbytes, A.head, A.nchunks, 0, D->lay.kind, A.elem1, dense};
         rc = add_req(b, reinterpret_cast<TypeNode *>(t), d, dense ? D->lay.rec.lds_bytes : 0);
         if (rc) return rc;
     }
@@ -471,7 +467,7 @@ MDT_API int mdt_batch_add_unpack(mdt_batch b, const void *inbuf, mdt_count insiz
         XferArgs A = make_args(outbuf, const_cast<void *>(inbuf), outoffset, insize);
         A.elem1 = A.off + A.nbytes <= D->lay.size;
         int dense = use_dense(D->lay, A, true);
-        ReqDesc d{D->d_lay, A.typed, A.packed, A.off, A.nbytes, A.head, A.nchunks, 1, D->lay.kind, A.elem1, dense};
+        ReqDesc d{(uint64_t)(uintptr_t)D->d_lay, A.typed, A.packed, A.off, A.nbytes, A.head, A.nchunks, 1, D->lay.kind, A.elem1, dense};
         rc = add_req(b, reinterpret_cast<TypeNode *>(t), d, dense ? D->lay.rec.lds_bytes : 0);
         if (rc) return rc;
     }

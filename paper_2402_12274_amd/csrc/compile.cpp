@@ -762,28 +762,14 @@ void lower_records(const Layout &L, Compiled &C)
         hi = std::max(hi, r.off + r.len);
     }
     if (hi - lo > 65535) return;
-    // LDS for a tile: typed span (+ slack) + packed tile, and both tables
-    static const int tc_max = [] {
-        const char *e = getenv("MDT_DENSE_TILE");
-        int v = e && *e ? atoi(e) : 1024;
-        return v >= 64 && v <= 2048 ? v : 1024;
-    }();
-    int tc = tc_max;
-    auto need = [&](int c) {
-        int64_t nrec = (16 * (int64_t)c + U - 1) / U + 1;
-        int64_t span = (nrec - 1) * X + (hi - lo) + 48;
-        int64_t pk = 16 * (int64_t)c + 48;
-        return ((std::max(span, pk) + 15) & ~(int64_t)15) + 4 * std::max<int64_t>(U, X) + 16;
-    };
-    while (tc > 64 && need(tc) > 40 * 1024) tc /= 2;
-    if (need(tc) > 40 * 1024) return;
+    // packed -> typed byte table (pack)
     C.rec_ptab.assign((size_t)U, 0);
     int64_t q = 0;
     for (const Run &r : S.leaf)
         for (int64_t i = 0; i < r.len; i++, q++)
             C.rec_ptab[q] = (uint32_t)(r.off + i - lo) | (uint32_t)(r.len - i) << 16;
-    // typed -> packed table (unpack), when records do not interleave and no
-    // byte of a record is covered twice
+    // typed -> packed byte table (unpack), when records do not interleave and
+    // no byte of a record is covered twice
     bool ok = hi - lo <= X;
     if (ok) {
         C.rec_ttab.assign((size_t)X, 0);
@@ -798,6 +784,59 @@ void lower_records(const Layout &L, Compiled &C)
         }
     }
     if (!ok) C.rec_ttab.clear();
+    // chunk table: the 16 typed offsets of the packed chunk starting at q
+    const bool ctab = U <= REC_CTAB_MAX_U;
+    C.rec_ctab.clear();
+    if (ctab) {
+        C.rec_ctab.resize((size_t)U * 16);
+        for (int64_t qq = 0; qq < U; qq++)
+            for (int64_t j = 0; j < 16; j++) {
+                int64_t pos = qq + j, rr = pos / U;
+                C.rec_ctab[(size_t)(qq * 16 + j)] = (C.rec_ptab[(size_t)(pos - rr * U)] & 0xffffu) + (uint32_t)(rr * X);
+            }
+    }
+    // dword table: packed offsets and coverage of typed bytes d .. d + 3
+    const bool dtab = ok && X >= 4 && X <= REC_DTAB_MAX_X;
+    C.rec_dtab.clear();
+    if (dtab) {
+        C.rec_dtab.assign((size_t)X * 4, 0);
+        for (int64_t d = 0; d < X; d++) {
+            uint32_t *e = &C.rec_dtab[(size_t)(4 * d)];
+            for (int i = 0; i < 4; i++) {
+                int64_t t = d + i, rr = t >= X ? 1 : 0;
+                uint32_t te = C.rec_ttab[(size_t)(t - rr * X)];
+                if (!(te & 0x80000000u)) continue;
+                uint32_t pq = (te & 0xffffu) + (uint32_t)(rr * U);
+                e[i >> 1] |= pq << (16 * (i & 1));
+                e[2] |= 1u << i;
+            }
+        }
+    }
+    // LDS for a tile: the table in front, then the typed span (pack) or the
+    // packed window (unpack), with slack for rounding out to 16-byte blocks
+    static const int tc_max = [] {
+        const char *e = getenv("MDT_DENSE_TILE");
+        int v = e && *e ? atoi(e) : 1024;
+        return v >= 64 && v <= 2048 ? v : 1024;
+    }();
+    auto a16 = [](int64_t n) { return (n + 15) & ~(int64_t)15; };
+    auto need = [&](int c) {
+        int64_t nrec = (16 * (int64_t)c + U - 1) / U + 1;
+        int64_t span = (nrec - 1) * X + (hi - lo) + 48;
+        int64_t np = a16(ctab ? 64 * U : 4 * U) + a16(span) + 16;
+        int64_t nu = 0;
+        if (ok) nu = dtab ? a16(16 * X) + a16(16 * (int64_t)c + 4 * U + 64) + 16 : a16(4 * X) + a16(16 * (int64_t)c + 48) + 16;
+        return std::max(np, nu);
+    };
+    int tc = tc_max;
+    while (tc > 64 && need(tc) > 40 * 1024) tc /= 2;
+    if (need(tc) > 40 * 1024) {
+        C.rec_ptab.clear();
+        C.rec_ttab.clear();
+        C.rec_ctab.clear();
+        C.rec_dtab.clear();
+        return;
+    }
     R.on = 1;
     R.U = (int32_t)U;
     R.X = (int32_t)X;
@@ -812,6 +851,8 @@ void lower_records(const Layout &L, Compiled &C)
     R.lds_bytes = (int32_t)need(tc);
     R.ptab = C.rec_ptab.data();
     R.ttab = ok ? C.rec_ttab.data() : nullptr;
+    R.ctab = ctab ? C.rec_ctab.data() : nullptr;
+    R.dtab = dtab ? C.rec_dtab.data() : nullptr;
     C.rec_count1_only = count1;
     R.count1_only = count1;
 }

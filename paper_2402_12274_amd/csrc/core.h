@@ -85,6 +85,7 @@ struct Compiled {
     std::vector<DevShape> shapes;
     std::vector<std::vector<int64_t>> leaf_store;  // big leaf arrays (off, len, pre per shape)
     std::vector<uint32_t> rec_ptab, rec_ttab;       // record-view byte tables
+    std::vector<uint32_t> rec_ctab, rec_dtab;       // record-view chunk (pack) and dword (unpack) tables
     bool rec_count1_only = false;                   // record view holds for element 0 only
     int64_t nruns = 0;
     bool merge_free = true;

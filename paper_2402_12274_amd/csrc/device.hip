@@ -94,6 +94,8 @@ int device_tables(Compiled *c, DeviceTables **out)
     size_t off_gdir = off; off += al256(c->gdir.size() * sizeof(int32_t));
     size_t off_ptab = off; off += al256(c->rec_ptab.size() * sizeof(uint32_t));
     size_t off_ttab = off; off += al256(c->rec_ttab.size() * sizeof(uint32_t));
+    size_t off_ctab = off; off += al256(c->rec_ctab.size() * sizeof(uint32_t));
+    size_t off_dtab = off; off += al256(c->rec_dtab.size() * sizeof(uint32_t));
     size_t off_lay = off; off += al256(sizeof(DevLayout));
     std::vector<uint8_t> blob(off, 0);
     uint8_t *base = nullptr;
@@ -128,6 +130,8 @@ int device_tables(Compiled *c, DeviceTables **out)
     put(off_gdir, c->gdir.data(), c->gdir.size() * 4);
     put(off_ptab, c->rec_ptab.data(), c->rec_ptab.size() * 4);
     put(off_ttab, c->rec_ttab.data(), c->rec_ttab.size() * 4);
+    put(off_ctab, c->rec_ctab.data(), c->rec_ctab.size() * 4);
+    put(off_dtab, c->rec_dtab.data(), c->rec_dtab.size() * 4);
     DevLayout &L = d->lay;
     if (nsh) L.shape0 = shapes[0];
     L.shapes = nsh ? (const DevShape *)(base + off_shapes) : nullptr;
@@ -138,6 +142,8 @@ int device_tables(Compiled *c, DeviceTables **out)
     L.gdir = H.gdir ? (const int32_t *)(base + off_gdir) : nullptr;
     L.rec.ptab = H.rec.ptab ? (const uint32_t *)(base + off_ptab) : nullptr;
     L.rec.ttab = H.rec.ttab ? (const uint32_t *)(base + off_ttab) : nullptr;
+    L.rec.ctab = H.rec.ctab ? (const uint32_t *)(base + off_ctab) : nullptr;
+    L.rec.dtab = H.rec.dtab ? (const uint32_t *)(base + off_dtab) : nullptr;
     std::memcpy(blob.data() + off_lay, &L, sizeof(DevLayout));
     d->d_lay = (DevLayout *)(base + off_lay);
     e = hipMemcpy(base, blob.data(), off, hipMemcpyHostToDevice);

@@ -29,6 +29,21 @@
 
 namespace mdt {
 
+// Element i of a table in device memory.  In device code the read goes
+// through a global-address-space pointer, so it compiles to a global load
+// rather than a flat one (flat accesses also count against the LDS wait
+// counter, which would make every LDS wait drain outstanding memory reads).
+template <class T>
+MDT_HD T gld(const T *p, int64_t i)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((const __attribute__((address_space(1))) T *)p)[i];
+#else
+    return p[i];
+#endif
+}
+
+
 constexpr int MAXO = 4;   // outer loops
 constexpr int MAXI = 4;   // inner loops per shape
 constexpr int LEAFI = 8;  // leaf runs stored inline in a shape
@@ -151,7 +166,18 @@ struct DevRecords {
     int32_t lds_bytes;   // dynamic LDS for that tile (spans + table)
     const uint32_t *ptab;  // [U] packed q -> (typed offset - lo) | (run bytes left from q) << 16
     const uint32_t *ttab;  // [X] typed offset d - lo -> q | (run bytes left) << 16 | valid << 31
+    // chunk table (pack, U <= REC_CTAB_MAX_U): [U][16] typed offsets, relative
+    // to lo of the record holding packed q, of packed bytes q .. q + 15
+    const uint32_t *ctab;
+    // dword table (unpack, 4 <= X <= REC_DTAB_MAX_X): [X][4] for typed bytes
+    // d .. d + 3 (relative to lo; past X they belong to the next record):
+    // packed offsets from the record's packed start (+ U in the next record),
+    // two 16-bit halves per word, then the mask of bytes the typemap covers
+    const uint32_t *dtab;
 };
+
+constexpr int32_t REC_CTAB_MAX_U = 256;
+constexpr int32_t REC_DTAB_MAX_X = 1024;
 
 enum LayoutKind : int32_t {
     KIND_EMPTY = 0,   // no bytes
@@ -213,11 +239,11 @@ MDT_HD Leaf leaf_of(const DevShape &S, uint64_t q)
         int lo = 0, hi = S.nleaf - 1;
         while (lo < hi) {
             int mid = (lo + hi + 1) >> 1;
-            if ((uint64_t)S.lpre_p[mid] <= q) lo = mid; else hi = mid - 1;
+            if ((uint64_t)gld(S.lpre_p, mid) <= q) lo = mid; else hi = mid - 1;
         }
-        r.off = S.loff_p[lo];
-        r.len = S.llen_p[lo];
-        r.pre = S.lpre_p[lo];
+        r.off = gld(S.loff_p, lo);
+        r.len = gld(S.llen_p, lo);
+        r.pre = gld(S.lpre_p, lo);
         return r;
     }
     r.off = S.loff[0];
@@ -239,9 +265,9 @@ MDT_HD Leaf leaf_at(const DevShape &S, uint64_t j)
 {
     Leaf r;
     if (S.nleaf > LEAFI) {
-        r.off = S.loff_p[j];
-        r.len = S.llen_p[j];
-        r.pre = S.lpre_p[j];
+        r.off = gld(S.loff_p, j);
+        r.len = gld(S.llen_p, j);
+        r.pre = gld(S.lpre_p, j);
         return r;
     }
     r.off = S.loff[0];
@@ -305,11 +331,11 @@ MDT_HD Loc locate_in_shape(const DevShape &S, uint64_t q, int64_t glen, int64_t 
 MDT_HD int64_t find_group(const DevLayout &L, uint64_t q)
 {
     int64_t k = (int64_t)(q >> L.dir_shift);
-    int64_t lo = L.gdir[k];
-    int64_t hi = (k + 1 < L.ndir) ? L.gdir[k + 1] : L.G - 1;
+    int64_t lo = gld(L.gdir, k);
+    int64_t hi = (k + 1 < L.ndir) ? gld(L.gdir, k + 1) : L.G - 1;
     while (lo < hi) {
         int64_t mid = (lo + hi + 1) >> 1;
-        if ((uint64_t)L.gpre[mid] <= q) lo = mid; else hi = mid - 1;
+        if ((uint64_t)gld(L.gpre, mid) <= q) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
@@ -342,11 +368,11 @@ MDT_HD Loc locate(const DevLayout &L, uint64_t p, bool elem1 = false)
         }
     }
     int64_t g = find_group(L, q);
-    int64_t g0 = L.gpre[g];
-    int64_t glen = L.gpre[g + 1] - g0;
+    int64_t g0 = gld(L.gpre, g);
+    int64_t glen = gld(L.gpre, g + 1) - g0;
     // shapes are read from the device table (never from the argument copy)
-    const DevShape &S = L.shapes[L.nshapes == 1 ? 0 : L.gshape[g]];
-    return locate_in_shape(S, q - (uint64_t)g0, glen, addr + L.gdisp[g]);
+    const DevShape &S = L.shapes[L.nshapes == 1 ? 0 : gld(L.gshape, g)];
+    return locate_in_shape(S, q - (uint64_t)g0, glen, addr + gld(L.gdisp, g));
 }
 
 MDT_HD Loc locate_any(const DevLayout &L, uint64_t p)
@@ -386,12 +412,12 @@ MDT_HD RunInfo run_at(const DevLayout &L, uint64_t k)
         int64_t lo = 0, hi = L.G - 1;
         while (lo < hi) {
             int64_t mid = (lo + hi + 1) >> 1;
-            if ((uint64_t)L.grpre[mid] <= k) lo = mid; else hi = mid - 1;
+            if ((uint64_t)gld(L.grpre, mid) <= k) lo = mid; else hi = mid - 1;
         }
-        k -= (uint64_t)L.grpre[lo];
-        addr += L.gdisp[lo];
-        glen = L.gpre[lo + 1] - L.gpre[lo];
-        S = &L.shapes[L.nshapes == 1 ? 0 : L.gshape[lo]];
+        k -= (uint64_t)gld(L.grpre, lo);
+        addr += gld(L.gdisp, lo);
+        glen = gld(L.gpre, lo + 1) - gld(L.gpre, lo);
+        S = &L.shapes[L.nshapes == 1 ? 0 : gld(L.gshape, lo)];
     }
     if (S->varlen) {
         r.addr = addr;

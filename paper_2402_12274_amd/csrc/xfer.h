@@ -19,6 +19,22 @@ struct V4 {
     uint32_t w0, w1, w2, w3;
 };
 
+// Global-address-space view of a generic pointer into device memory: loads
+// and stores through it compile to global_* instructions.  Flat ones would
+// also count against the LDS wait counter, so every LDS wait in a tile would
+// drain the tile's outstanding memory traffic as well.
+#define MDT_G __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ MDT_G T *gptr(T *p)
+{
+    return (MDT_G T *)p;
+}
+template <class T>
+__device__ __forceinline__ const MDT_G T *gptr(const T *p)
+{
+    return (const MDT_G T *)p;
+}
+
 // Byte / dword extraction at a variable byte position of the chunk, as
 // 128-bit shifts (funnel shifts in registers; an indexed select would be
 // turned into a per-lane memory array).
@@ -43,17 +59,17 @@ __device__ __forceinline__ V4 load16(const uint8_t *s)
     uintptr_t u = (uintptr_t)s;
     V4 r;
     if ((u & 15) == 0) {
-        u32x4 v = __builtin_nontemporal_load((const u32x4 *)s);
+        u32x4 v = __builtin_nontemporal_load(gptr((const u32x4 *)s));
         r.w0 = v.x; r.w1 = v.y; r.w2 = v.z; r.w3 = v.w;
     } else if ((u & 7) == 0) {
-        const u32x2 *p = (const u32x2 *)s;
+        const MDT_G u32x2 *p = gptr((const u32x2 *)s);
         u32x2 a = p[0], b = p[1];
         r.w0 = a.x; r.w1 = a.y; r.w2 = b.x; r.w3 = b.y;
     } else if ((u & 3) == 0) {
-        const uint32_t *p = (const uint32_t *)s;
+        const MDT_G uint32_t *p = gptr((const uint32_t *)s);
         r.w0 = p[0]; r.w1 = p[1]; r.w2 = p[2]; r.w3 = p[3];
     } else {
-        const uint32_t *p = (const uint32_t *)(u & ~(uintptr_t)3);
+        const MDT_G uint32_t *p = gptr((const uint32_t *)(u & ~(uintptr_t)3));
         uint32_t sh = (uint32_t)(u & 3);
         uint32_t d0 = p[0], d1 = p[1], d2 = p[2], d3 = p[3], d4 = p[4];
         r.w0 = __builtin_amdgcn_alignbyte(d1, d0, sh);
@@ -71,7 +87,7 @@ __device__ __forceinline__ uint32_t gather_word(int t, int k, const uint8_t *s, 
     int a = max(4 * t, k), b = min(4 * t + 4, k + n);
     if (a >= b) return 0u;
     uintptr_t u = (uintptr_t)(s + (a - k));
-    const uint32_t *p = (const uint32_t *)(u & ~(uintptr_t)3);
+    const MDT_G uint32_t *p = gptr((const uint32_t *)(u & ~(uintptr_t)3));
     uint32_t sh = (uint32_t)(u & 3);
     int cnt = b - a;
     uint32_t lo = p[0];
@@ -97,27 +113,28 @@ __device__ __forceinline__ void scatter(const V4 &acc, int k, uint8_t *d, int n)
     if (n == 16) {
         if ((u & 15) == 0) {
             u32x4 v = {acc.w0, acc.w1, acc.w2, acc.w3};
-            *(u32x4 *)d = v;
+            *gptr((u32x4 *)d) = v;
             return;
         }
         if ((u & 7) == 0) {
-            u32x2 *p = (u32x2 *)d;
+            MDT_G u32x2 *p = gptr((u32x2 *)d);
             p[0] = u32x2{acc.w0, acc.w1};
             p[1] = u32x2{acc.w2, acc.w3};
             return;
         }
         if ((u & 3) == 0) {
-            uint32_t *p = (uint32_t *)d;
+            MDT_G uint32_t *p = gptr((uint32_t *)d);
             p[0] = acc.w0; p[1] = acc.w1; p[2] = acc.w2; p[3] = acc.w3;
             return;
         }
     }
     int h = (int)((4 - (u & 3)) & 3);
     if (h > n) h = n;
-    for (int i = 0; i < h; i++) d[i] = (uint8_t)byte_at(acc, k + i);
+    MDT_G uint8_t *g = gptr(d);
+    for (int i = 0; i < h; i++) g[i] = (uint8_t)byte_at(acc, k + i);
     int j = h;
-    for (; j + 4 <= n; j += 4) *(uint32_t *)(d + j) = dword_at(acc, k + j);
-    for (; j < n; j++) d[j] = (uint8_t)byte_at(acc, k + j);
+    for (; j + 4 <= n; j += 4) *gptr((uint32_t *)(d + j)) = dword_at(acc, k + j);
+    for (; j < n; j++) g[j] = (uint8_t)byte_at(acc, k + j);
 }
 
 // ---------------------------------------------------------------------------
@@ -152,9 +169,9 @@ __device__ __forceinline__ void pack_chunk(const DevLayout &L, const XferArgs &A
     uint8_t *dst = A.packed - A.head + 16 * c;
     if (a == lo && b == lo + 16) {
         u32x4 v = {acc.w0, acc.w1, acc.w2, acc.w3};
-        __builtin_nontemporal_store(v, (u32x4 *)dst);
+        __builtin_nontemporal_store(v, gptr((u32x4 *)dst));
     } else {
-        for (int i = (int)(a - lo); i < (int)(b - lo); i++) dst[i] = (uint8_t)byte_at(acc, i);
+        for (int i = (int)(a - lo); i < (int)(b - lo); i++) gptr(dst)[i] = (uint8_t)byte_at(acc, i);
     }
 }
 
@@ -168,7 +185,7 @@ __device__ __forceinline__ void unpack_chunk(const DevLayout &L, const XferArgs 
     int n = (int)(b - a);
     // the aligned 16-byte block holding this chunk's packed bytes
     const uint8_t *in = A.packed - A.head + 16 * c;
-    u32x4 v = __builtin_nontemporal_load((const u32x4 *)in);
+    u32x4 v = __builtin_nontemporal_load(gptr((const u32x4 *)in));
     V4 acc = {v.x, v.y, v.z, v.w};
     uint64_t p = (uint64_t)(A.off + a);
     uint8_t *dst = const_cast<uint8_t *>(A.typed);
@@ -206,7 +223,86 @@ __device__ __forceinline__ bool pack_first(const DevLayout &L, const XferArgs &A
 __device__ __forceinline__ void store_chunk(const XferArgs &A, int64_t c, const V4 &acc)
 {
     u32x4 v = {acc.w0, acc.w1, acc.w2, acc.w3};
-    __builtin_nontemporal_store(v, (u32x4 *)(A.packed - A.head + 16 * c));
+    __builtin_nontemporal_store(v, gptr((u32x4 *)(A.packed - A.head + 16 * c)));
+}
+
+// Whole tile inside one run: the typed address of packed byte lo (relative
+// to the packed start) is base + lo.  Returns false when the tile's bytes
+// span several runs (or the layout is contiguous, which needs no test).
+template <int KIND>
+__device__ __forceinline__ bool tile_in_one_run(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t cend,
+                                                int64_t &base)
+{
+    const int64_t P_lo = max(16 * c0 - A.head, (int64_t)0);
+    const int64_t P_hi = min(16 * cend - A.head, A.nbytes);
+    Loc l = locate<KIND>(L, (uint64_t)(A.off + P_lo), A.elem1);
+    base = l.addr - P_lo;
+    return l.rem >= P_hi - P_lo;
+}
+
+template <int KIND>
+__device__ __forceinline__ void pack_tile_run(const XferArgs &A, int64_t c0, int64_t cend, int64_t base)
+{
+    const int64_t c = c0 + threadIdx.x;
+    V4 a0 = {0u, 0u, 0u, 0u}, a1 = a0, a2 = a0, a3 = a0;
+    uint32_t full = 0;
+#define MDT_RUN_LOAD(k, a)                                                   \
+    {                                                                        \
+        int64_t ck = c + 256 * (k), lo = 16 * ck - A.head;                   \
+        if (ck < cend && lo >= 0 && lo + 16 <= A.nbytes) {                   \
+            a = load16(A.typed + base + lo);                                 \
+            full |= 1u << (k);                                               \
+        }                                                                    \
+    }
+    MDT_RUN_LOAD(0, a0) MDT_RUN_LOAD(1, a1) MDT_RUN_LOAD(2, a2) MDT_RUN_LOAD(3, a3)
+#undef MDT_RUN_LOAD
+    if (full & 1u) store_chunk(A, c, a0);
+    if (full & 2u) store_chunk(A, c + 256, a1);
+    if (full & 4u) store_chunk(A, c + 512, a2);
+    if (full & 8u) store_chunk(A, c + 768, a3);
+#pragma unroll 1
+    for (int k = 0; k < 4; k++) {
+        int64_t ck = c + 256 * k;
+        if (ck >= cend || ((full >> k) & 1u)) continue;
+        // edge chunk of the transfer: byte by byte
+        const int64_t lo = 16 * ck - A.head;
+        const int64_t a = lo > 0 ? lo : 0, b = lo + 16 < A.nbytes ? lo + 16 : A.nbytes;
+        uint8_t *dst = A.packed - A.head + 16 * ck;
+        for (int64_t j = a; j < b; j++) gptr(dst)[j - lo] = gptr(A.typed)[base + j];
+    }
+}
+
+template <int KIND>
+__device__ __forceinline__ void unpack_tile_run(const XferArgs &A, int64_t c0, int64_t cend, int64_t base)
+{
+    const int64_t c = c0 + threadIdx.x;
+    uint8_t *typed = const_cast<uint8_t *>(A.typed);
+    V4 a0 = {0u, 0u, 0u, 0u}, a1 = a0, a2 = a0, a3 = a0;
+    uint32_t full = 0;
+#define MDT_RUN_LOAD(k, a)                                                               \
+    {                                                                                    \
+        int64_t ck = c + 256 * (k), lo = 16 * ck - A.head;                               \
+        if (ck < cend && lo >= 0 && lo + 16 <= A.nbytes) {                               \
+            u32x4 v = __builtin_nontemporal_load(gptr((const u32x4 *)(A.packed - A.head + 16 * ck))); \
+            a = V4{v.x, v.y, v.z, v.w};                                                  \
+            full |= 1u << (k);                                                           \
+        }                                                                                \
+    }
+    MDT_RUN_LOAD(0, a0) MDT_RUN_LOAD(1, a1) MDT_RUN_LOAD(2, a2) MDT_RUN_LOAD(3, a3)
+#undef MDT_RUN_LOAD
+    if (full & 1u) scatter(a0, 0, typed + base + (16 * c - A.head), 16);
+    if (full & 2u) scatter(a1, 0, typed + base + (16 * (c + 256) - A.head), 16);
+    if (full & 4u) scatter(a2, 0, typed + base + (16 * (c + 512) - A.head), 16);
+    if (full & 8u) scatter(a3, 0, typed + base + (16 * (c + 768) - A.head), 16);
+#pragma unroll 1
+    for (int k = 0; k < 4; k++) {
+        int64_t ck = c + 256 * k;
+        if (ck >= cend || ((full >> k) & 1u)) continue;
+        const int64_t lo = 16 * ck - A.head;
+        const int64_t a = lo > 0 ? lo : 0, b = lo + 16 < A.nbytes ? lo + 16 : A.nbytes;
+        const uint8_t *src = A.packed - A.head + 16 * ck;
+        for (int64_t j = a; j < b; j++) gptr(typed)[base + j] = gptr(src)[j - lo];
+    }
 }
 
 // A lane's chunks c0 + lane + 256k (k < 4) of a tile, loads first: every
@@ -216,6 +312,13 @@ __device__ __forceinline__ void store_chunk(const XferArgs &A, int64_t c, const 
 template <int KIND>
 __device__ __forceinline__ void pack_tile4(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t cend)
 {
+    if (KIND != KIND_CONTIG) {
+        int64_t base;
+        if (tile_in_one_run<KIND>(L, A, c0, cend, base)) {
+            pack_tile_run<KIND>(A, c0, cend, base);
+            return;
+        }
+    }
     const int64_t c = c0 + threadIdx.x;
     V4 a0 = {0u, 0u, 0u, 0u}, a1 = a0, a2 = a0, a3 = a0;
     uint32_t fast = (uint32_t)pack_first<KIND>(L, A, c, cend, a0) | (uint32_t)pack_first<KIND>(L, A, c + 256, cend, a1) << 1 |
@@ -238,7 +341,7 @@ __device__ __forceinline__ bool unpack_first(const DevLayout &L, const XferArgs 
 {
     int64_t lo = 16 * c - A.head;
     if (c < cend && lo >= 0 && lo + 16 <= A.nbytes) {
-        u32x4 v = __builtin_nontemporal_load((const u32x4 *)(A.packed - A.head + 16 * c));
+        u32x4 v = __builtin_nontemporal_load(gptr((const u32x4 *)(A.packed - A.head + 16 * c)));
         acc = V4{v.x, v.y, v.z, v.w};
         loc = locate<KIND>(L, (uint64_t)(A.off + lo), A.elem1);
         return loc.rem >= 16;
@@ -249,6 +352,13 @@ __device__ __forceinline__ bool unpack_first(const DevLayout &L, const XferArgs 
 template <int KIND>
 __device__ __forceinline__ void unpack_tile4(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t cend)
 {
+    if (KIND != KIND_CONTIG) {
+        int64_t base;
+        if (tile_in_one_run<KIND>(L, A, c0, cend, base)) {
+            unpack_tile_run<KIND>(A, c0, cend, base);
+            return;
+        }
+    }
     const int64_t c = c0 + threadIdx.x;
     uint8_t *dst = const_cast<uint8_t *>(A.typed);
     V4 a0 = {0u, 0u, 0u, 0u}, a1 = a0, a2 = a0, a3 = a0;
@@ -299,7 +409,7 @@ __device__ __forceinline__ uint32_t stage_span(uint8_t *lds, const uint8_t *g_lo
     uintptr_t b = ((uintptr_t)g_hi + 15) & ~(uintptr_t)15;
     uint32_t nv = (uint32_t)((b - a) >> 4);
     for (uint32_t i = threadIdx.x; i < nv; i += blockDim.x) {
-        u32x4 v = __builtin_nontemporal_load((const u32x4 *)(a + 16 * (uintptr_t)i));
+        u32x4 v = __builtin_nontemporal_load(gptr((const u32x4 *)(a + 16 * (uintptr_t)i)));
         *(u32x4 *)(lds + 16 * i) = v;
     }
     return (uint32_t)((uintptr_t)g_lo - a);
@@ -332,9 +442,9 @@ __device__ __forceinline__ uint32_t dense_word(const uint32_t *tab, const uint8_
     return v;
 }
 
-// Pack chunks [c0, c1) of A (a tile) with the record view of L.  `lds`
-// holds rec.lds_bytes of dynamic shared memory.
-__device__ __forceinline__ void dense_pack_tile(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t c1,
+// Pack chunks [c0, c1) of A (a tile) with the record view of L and its byte
+// table.  `lds` holds rec.lds_bytes of dynamic shared memory.
+__device__ __forceinline__ void dense_pack_tile_b(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t c1,
                                                 uint8_t *lds)
 {
     const DevRecords &R = L.rec;
@@ -347,7 +457,7 @@ __device__ __forceinline__ void dense_pack_tile(const DevLayout &L, const XferAr
     const int64_t t_hi = R.B0 + (int64_t)e1 * R.X + R.hi;
     uint32_t *tab = (uint32_t *)lds;
     uint8_t *span = lds + ((4 * (uint32_t)R.U + 15) & ~15u);
-    for (int q = threadIdx.x; q < R.U; q += blockDim.x) tab[q] = R.ptab[q];
+    for (int q = threadIdx.x; q < R.U; q += blockDim.x) tab[q] = gld(R.ptab, q);
     const uint32_t base = stage_span(span, A.typed + t_lo, A.typed + t_hi);
     __syncthreads();
     const uint32_t q0 = (uint32_t)(s_lo - e0 * (uint64_t)R.U);  // position of s_lo in record e0
@@ -366,22 +476,22 @@ __device__ __forceinline__ void dense_pack_tile(const DevLayout &L, const XferAr
             uint32_t w2 = dense_word(tab, span, base, X, U, q, er);
             uint32_t w3 = dense_word(tab, span, base, X, U, q, er);
             u32x4 v = {w0, w1, w2, w3};
-            __builtin_nontemporal_store(v, (u32x4 *)(A.packed - A.head + 16 * c));
+            __builtin_nontemporal_store(v, gptr((u32x4 *)(A.packed - A.head + 16 * c)));
         } else {
             uint8_t *dst = A.packed - A.head + 16 * c;
             for (int i = (int)(a - lo); i < (int)(b - lo); i++) {
                 uint32_t ei = tab[q];
-                dst[i] = (uint8_t)lds_u8(span, base + er * X + (ei & 0xffffu));
+                gptr(dst)[i] = (uint8_t)lds_u8(span, base + er * X + (ei & 0xffffu));
                 if (++q == U) { q = 0; er++; }
             }
         }
     }
 }
 
-// Unpack chunks [c0, c1) of A (a tile): the packed tile goes to LDS, then the
-// lanes walk the typed span dword by dword and store the typemap bytes that
-// belong to this tile.
-__device__ __forceinline__ void dense_unpack_tile(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t c1,
+// Unpack chunks [c0, c1) of A (a tile) with the byte table: the packed tile
+// goes to LDS, then the lanes walk the typed span dword by dword and store
+// the typemap bytes that belong to this tile.
+__device__ __forceinline__ void dense_unpack_tile_b(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t c1,
                                                   uint8_t *lds)
 {
     const DevRecords &R = L.rec;
@@ -394,7 +504,7 @@ __device__ __forceinline__ void dense_unpack_tile(const DevLayout &L, const Xfer
     const int64_t t_hi = R.B0 + (int64_t)e1 * R.X + R.hi;
     uint32_t *tab = (uint32_t *)lds;
     uint8_t *pk = lds + ((4 * (uint32_t)R.X + 15) & ~15u);
-    for (int d = threadIdx.x; d < R.X; d += blockDim.x) tab[d] = R.ttab[d];
+    for (int d = threadIdx.x; d < R.X; d += blockDim.x) tab[d] = gld(R.ttab, d);
     const uint32_t pbase = stage_span(pk, A.packed + P_lo, A.packed + P_hi);
     __syncthreads();
     const uint32_t U = (uint32_t)R.U, X = (uint32_t)R.X;
@@ -415,7 +525,7 @@ __device__ __forceinline__ void dense_unpack_tile(const DevLayout &L, const Xfer
             // packed offset in this tile = er*U + q - q0
             int32_t p = (int32_t)(er * U + (e & 0xffffu)) - (int32_t)q0;
             if ((e & 0x80000000u) && ((e >> 16) & 0x7fffu) >= 4u && p >= 0 && (uint32_t)p + 4 <= npk) {
-                *D = lds_u32(pk, pbase + (uint32_t)p);
+                *gptr(D) = lds_u32(pk, pbase + (uint32_t)p);
                 continue;
             }
         }
@@ -430,9 +540,148 @@ __device__ __forceinline__ void dense_unpack_tile(const DevLayout &L, const Xfer
             if (!(e & 0x80000000u)) continue;
             int32_t p = (int32_t)(er * U + (e & 0xffffu)) - (int32_t)q0;
             if (p < 0 || (uint32_t)p >= npk) continue;
-            Db[i] = (uint8_t)lds_u8(pk, pbase + (uint32_t)p);
+            gptr(Db)[i] = (uint8_t)lds_u8(pk, pbase + (uint32_t)p);
         }
     }
+}
+
+// Four LDS bytes at rb + o.{x,y,z,w}, as one little-endian word.
+__device__ __forceinline__ uint32_t lds_gather4(const uint8_t *lds, uint32_t rb, const uint4 &o)
+{
+    uint32_t b0 = lds[rb + o.x], b1 = lds[rb + o.y], b2 = lds[rb + o.z], b3 = lds[rb + o.w];
+    return b0 | b1 << 8 | b2 << 16 | b3 << 24;
+}
+
+// Pack chunks [c0, c1) of A with the chunk table: one division per chunk
+// finds the record and phase of its first byte, the table entry of that
+// phase gives the 16 typed offsets, and the bytes are gathered from the
+// staged span.  Only the two edge chunks of a transfer go byte by byte.
+__device__ __forceinline__ void dense_pack_tile_c(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t c1,
+                                                  uint8_t *lds)
+{
+    const DevRecords &R = L.rec;
+    const int64_t P_lo = max(16 * c0 - A.head, (int64_t)0);
+    const int64_t P_hi = min(16 * c1 - A.head, A.nbytes);
+    const uint64_t s_lo = (uint64_t)(A.off + P_lo);
+    const uint64_t e0 = magic_div(s_lo, R.dU);
+    const uint64_t e1 = magic_div((uint64_t)(A.off + P_hi - 1), R.dU);
+    const int64_t t_lo = R.B0 + (int64_t)e0 * R.X + R.lo;
+    const int64_t t_hi = R.B0 + (int64_t)e1 * R.X + R.hi;
+    const uint32_t U = (uint32_t)R.U, X = (uint32_t)R.X;
+    uint32_t *tab = (uint32_t *)lds;
+    uint8_t *span = lds + 64 * U;
+    for (uint32_t i = threadIdx.x; i < 4 * U; i += blockDim.x) ((uint4 *)tab)[i] = gld((const uint4 *)R.ctab, i);
+    const uint32_t base = stage_span(span, A.typed + t_lo, A.typed + t_hi);
+    __syncthreads();
+    const uint32_t q0 = (uint32_t)(s_lo - e0 * (uint64_t)U);  // phase of s_lo in record e0
+    const int32_t r00 = (int32_t)(16 * c0 - A.head - P_lo);   // chunk c0's start, from P_lo (-15 .. 0)
+    const int32_t npk = (int32_t)(P_hi - P_lo);
+    uint8_t *const out = A.packed - A.head + 16 * c0;
+    const uint32_t nc = (uint32_t)(c1 - c0);
+    for (uint32_t k = threadIdx.x; k < nc; k += blockDim.x) {
+        const int32_t pr = r00 + 16 * (int32_t)k;
+        if (pr >= 0 && pr + 16 <= npk) {
+            const uint32_t rel = (uint32_t)pr + q0;
+            const uint32_t er = magic_div32(rel, R.dU32);
+            const uint32_t q = rel - er * U;
+            const uint32_t rb = base + er * X;
+            const uint4 *e = (const uint4 *)(tab + 16 * q);
+            const uint4 o0 = e[0], o1 = e[1], o2 = e[2], o3 = e[3];
+            u32x4 v = {lds_gather4(span, rb, o0), lds_gather4(span, rb, o1), lds_gather4(span, rb, o2),
+                       lds_gather4(span, rb, o3)};
+            __builtin_nontemporal_store(v, gptr((u32x4 *)(out + 16 * k)));
+        } else {
+            const int32_t a = pr > 0 ? pr : 0, b = pr + 16 < npk ? pr + 16 : npk;
+            for (int32_t i = a; i < b; i++) {
+                const uint32_t rel = (uint32_t)i + q0;
+                const uint32_t er = magic_div32(rel, R.dU32);
+                const uint32_t q = rel - er * U;
+                gptr(out)[16 * k + (uint32_t)(i - pr)] = span[base + er * X + tab[16 * q]];
+            }
+        }
+    }
+}
+
+// Unpack chunks [c0, c1) of A with the dword table.  The LDS window holds
+// the packed bytes of records e0 - 1 .. e1 + 1 (clipped to the transfer), so
+// every typed dword that overlaps this tile's records can be assembled
+// whole: a dword shared with a neighbouring tile is written by both with the
+// same bytes.  Away from the transfer's ends nothing is clipped and no byte
+// needs a range test; gap bytes are never written.
+__device__ __forceinline__ void dense_unpack_tile_d(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t c1,
+                                                    uint8_t *lds)
+{
+    const DevRecords &R = L.rec;
+    const int64_t P_lo = max(16 * c0 - A.head, (int64_t)0);
+    const int64_t P_hi = min(16 * c1 - A.head, A.nbytes);
+    const uint64_t e0 = magic_div((uint64_t)(A.off + P_lo), R.dU);
+    const uint64_t e1 = magic_div((uint64_t)(A.off + P_hi - 1), R.dU);
+    const int64_t t_lo = R.B0 + (int64_t)e0 * R.X + R.lo;
+    const int64_t t_hi = R.B0 + (int64_t)e1 * R.X + R.hi;
+    const uint32_t U = (uint32_t)R.U, X = (uint32_t)R.X;
+    // window [W0, W1) in transfer-relative packed positions, and its clip
+    const int64_t W0 = ((int64_t)e0 - 1) * U - A.off;
+    const int64_t W1 = ((int64_t)e1 + 2) * U - A.off;
+    const int64_t Wc0 = W0 > 0 ? W0 : 0, Wc1 = W1 < A.nbytes ? W1 : A.nbytes;
+    const bool clipped = Wc0 != W0 || Wc1 != W1;
+    uint32_t *tab = (uint32_t *)lds;
+    uint8_t *pk = lds + 16 * X;
+    for (uint32_t i = threadIdx.x; i < X; i += blockDim.x) ((uint4 *)tab)[i] = gld((const uint4 *)R.dtab, i);
+    const uint32_t pbase = stage_span(pk, A.packed + Wc0, A.packed + Wc1);
+    __syncthreads();
+    // window position w (from W0) sits at LDS offset pbase + w - (Wc0 - W0);
+    // positions in [vlo, vhi) were staged
+    const uint32_t vlo = (uint32_t)(Wc0 - W0), vhi = (uint32_t)(Wc1 - W0);
+    uint8_t *t0 = const_cast<uint8_t *>(A.typed) + t_lo;  // typed byte of (record e0, offset lo)
+    const uintptr_t d_lo = (uintptr_t)t0 & ~(uintptr_t)3;
+    const uint32_t skew = (uint32_t)((uintptr_t)t0 - d_lo);
+    const uint32_t tspan = (uint32_t)(t_hi - t_lo);
+    const uint32_t ndw = (skew + tspan + 3) >> 2;
+    for (uint32_t j = threadIdx.x; j < ndw; j += blockDim.x) {
+        // typed offset of the dword from record e0 - 1's lo
+        const uint32_t r = 4 * j - skew + X;
+        const uint32_t er = magic_div32(r, R.dX32);
+        const uint32_t d = r - er * X;
+        const uint4 e = ((const uint4 *)tab)[d];
+        const uint32_t wb = er * U;  // window position of record e0 - 1 + er
+        uint32_t w0 = wb + (e.x & 0xffffu), w1 = wb + (e.x >> 16), w2 = wb + (e.y & 0xffffu), w3 = wb + (e.y >> 16);
+        uint32_t m = e.z;
+        if (clipped) {
+            m &= (w0 - vlo < vhi - vlo ? 1u : 0u) | (w1 - vlo < vhi - vlo ? 2u : 0u) |
+                 (w2 - vlo < vhi - vlo ? 4u : 0u) | (w3 - vlo < vhi - vlo ? 8u : 0u);
+            w0 = (m & 1u) ? w0 : vlo;
+            w1 = (m & 2u) ? w1 : vlo;
+            w2 = (m & 4u) ? w2 : vlo;
+            w3 = (m & 8u) ? w3 : vlo;
+        }
+        if (!m) continue;
+        const uint32_t sh = pbase - vlo;
+        const uint32_t v = lds_gather4(pk, sh, uint4{w0, w1, w2, w3});
+        uint8_t *D = (uint8_t *)(d_lo + 4 * (uintptr_t)j);
+        if (m == 15u) {
+            *gptr((uint32_t *)D) = v;
+        } else {
+            do {
+                const int i = __builtin_ctz(m);
+                gptr(D)[i] = (uint8_t)(v >> (8 * i));
+                m &= m - 1;
+            } while (m);
+        }
+    }
+}
+
+__device__ __forceinline__ void dense_pack_tile(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t c1,
+                                                uint8_t *lds)
+{
+    if (L.rec.ctab) dense_pack_tile_c(L, A, c0, c1, lds);
+    else dense_pack_tile_b(L, A, c0, c1, lds);
+}
+
+__device__ __forceinline__ void dense_unpack_tile(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t c1,
+                                                  uint8_t *lds)
+{
+    if (L.rec.dtab) dense_unpack_tile_d(L, A, c0, c1, lds);
+    else dense_unpack_tile_b(L, A, c0, c1, lds);
 }
 
 }  // namespace mdt
@@ -467,8 +716,8 @@ __device__ __forceinline__ int64_t runs_cache_fill(const DevLayout &L, const Xfe
     int64_t g1 = find_group(L, s_hi - 1 - ebase);
     int64_t n = g1 - g0 + 1;
     if (n > RUNS_CACHE) return -1;
-    for (int64_t i = threadIdx.x; i <= n; i += blockDim.x) C.pre[i] = L.gpre[g0 + i];
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) C.disp[i] = L.gdisp[g0 + i];
+    for (int64_t i = threadIdx.x; i <= n; i += blockDim.x) C.pre[i] = gld(L.gpre, g0 + i);
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) C.disp[i] = gld(L.gdisp, g0 + i);
     __syncthreads();
     return n;
 }
@@ -511,7 +760,7 @@ __device__ __forceinline__ void runs_tile(const DevLayout &L, const XferArgs &A,
         int i = runs_find(C, (int)n, q);
         V4 acc = {0u, 0u, 0u, 0u};
         if (UNPACK) {
-            u32x4 v = __builtin_nontemporal_load((const u32x4 *)(A.packed - A.head + 16 * c));
+            u32x4 v = __builtin_nontemporal_load(gptr((const u32x4 *)(A.packed - A.head + 16 * c)));
             acc = V4{v.x, v.y, v.z, v.w};
         }
         while (m > 0) {
@@ -534,9 +783,9 @@ __device__ __forceinline__ void runs_tile(const DevLayout &L, const XferArgs &A,
             uint8_t *dst = A.packed - A.head + 16 * c;
             if (a == lo && b == lo + 16) {
                 u32x4 v = {acc.w0, acc.w1, acc.w2, acc.w3};
-                __builtin_nontemporal_store(v, (u32x4 *)dst);
+                __builtin_nontemporal_store(v, gptr((u32x4 *)dst));
             } else {
-                for (int j = (int)(a - lo); j < (int)(b - lo); j++) dst[j] = (uint8_t)byte_at(acc, j);
+                for (int j = (int)(a - lo); j < (int)(b - lo); j++) gptr(dst)[j] = (uint8_t)byte_at(acc, j);
             }
         }
     }

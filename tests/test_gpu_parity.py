@@ -161,6 +161,73 @@ def test_particle_records_midsize(mdt):
     _layout_case(mdt, inputs.particle_struct(), count, count * 40, 0, seed=8, chunk=(1 << 16) - 1)
 
 
+def test_long_runs_partial(mdt):
+    # runs longer than a tile (whole tiles inside one run) with ragged edges:
+    # odd byte strides, misaligned output pointers, budgets off the 16-B grid
+    cases = [
+        (("subarray", [64, 4096], [40, 3001], [7, 13], "C", inputs.DOUBLE), 1, 64 * 4096 * 8, 0, (1 << 17) + 5),
+        (("hvector", 9, 20011, 20011 + 4099, inputs.BYTE), 2, 2 * 9 * 24110 + 64, 3, 40009),
+        (("vector", 5, 4100, 4100 + 3, ("basic", "FLOAT")), 3, 3 * 5 * 4103 * 4, 1, 1 << 16),
+    ]
+    for spec, count, nbytes, origin, chunk in cases:
+        note(f"long runs {spec[0]} count={count}")
+        _layout_case(mdt, spec, count, nbytes, origin, seed=count * 7 + 1, chunk=chunk)
+
+
+C, I16, I32, U8 = ("basic", "CHAR"), ("basic", "INT16"), ("basic", "INT32"), ("basic", "UINT8")
+RECORD_CASES = [
+    # (spec, count, origin, chunk): record views with odd strides, gaps at
+    # both ends of a record, map order unlike address order, and records
+    # large enough for the byte-table paths (U > 256 or X > 1024)
+    (("resized", 0, 9, ("struct", [1, 1, 1], [0, 2, 7], [C, I16, C])), 30001, 3, 4099),
+    (("hvector", 20000, 3, 4, U8), 1, 1, 5003),
+    (("hvector", 5000, 1, 12, I32), 1, 2, 1 << 12),
+    (("struct", [1, 1, 3], [16, 0, 8], [inputs.DOUBLE, I32, C]), 40000, 5, 65537),
+    (("resized", 0, 320, ("contiguous", 75, I32)), 3000, 0, (1 << 15) + 1),
+    (("resized", 0, 1100, ("struct", [1, 1], [0, 600], [("contiguous", 50, inputs.DOUBLE),
+                                                        ("contiguous", 100, I32)])), 500, 7, 30011),
+    (("resized", 0, 8, ("struct", [1, 1], [0, 12], [I32, I32])), 20000, 1, 9999),
+]
+
+
+@pytest.mark.parametrize("i", range(len(RECORD_CASES)))
+def test_record_layouts(mdt, i):
+    spec, count, origin, chunk = RECORD_CASES[i]
+    note(f"record layout {i}: {str(spec)[:70]} count={count}")
+    o = obuild(spec)
+    a = o.attrs()
+    nbytes = origin + (count - 1) * a["extent"] + a["true_ub"] + 16
+    _layout_case(mdt, spec, count, nbytes, origin, seed=100 + i, chunk=chunk)
+
+
+def test_record_split_unpack_in_one_batch(mdt):
+    # two halves of one stream unpacked into one buffer by one launch: the
+    # dword that straddles the split is assembled by both requests, each
+    # writing only the bytes of its own half
+    from gpu_util import torch_cuda
+
+    torch = torch_cuda()
+    spec = ("resized", 0, 9, ("struct", [1, 1, 1], [0, 2, 7], [C, I16, C]))
+    count = 20000
+    t = mdt.build_type(spec)
+    o = obuild(spec)
+    host = inputs.random_bytes(count * 9 + 16, seed=31)
+    full = o.pack(host, 0, count)
+    pk = to_dev(full)
+    ms = mdt.Stream(torch.cuda.current_stream().cuda_stream)
+    for split in (full.size // 2, 12345, 4 * 9 * 1000 + 1):
+        canary = np.full(host.size, 0x5A, np.uint8)
+        exp = canary.copy()
+        o.unpack(full, exp, 0, count)
+        dst = to_dev(canary)
+        b = mdt.Batch()
+        b.add_unpack(pk.data_ptr(), split, dst.data_ptr(), count, t, 0)
+        b.add_unpack(pk.data_ptr() + split, full.size - split, dst.data_ptr(), count, t, split)
+        b.launch(ms)
+        torch.cuda.synchronize()
+        assert first_diff(to_host(dst), exp) is None, split
+
+
 def test_contiguous_and_degenerate(mdt):
     note("contiguous / degenerate")
     host = inputs.random_bytes(1 << 20, seed=9)
