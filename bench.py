@@ -45,6 +45,9 @@ def parse():
                     choices=["halo", "particles", "hindexed", "contig", "rows", "small", "serve", "batch4096"])
     ap.add_argument("--duration", type=float, default=15.0, help="serve: seconds of trace per replay")
     ap.add_argument("--rate", type=float, default=20000.0, help="serve: Poisson arrival rate (requests/s)")
+    ap.add_argument("--sat-rate", type=float, default=150000.0,
+                    help="serve: a second, saturating arrival rate replayed after the first (0: skip)")
+    ap.add_argument("--sat-duration", type=float, default=2.0, help="serve: seconds of the saturating trace")
     ap.add_argument("--mode", default="batched", choices=["plain", "batched"])
     ap.add_argument("--rotate", type=int, default=4,
                     help="rotate over this many copies of the arrays so every step reads cold data")
@@ -145,7 +148,9 @@ def copy_ceiling_gbs(torch, dev, nbytes=1 << 30, reps=10):
 
 def serve_bench(args, torch, mdt):
     """Serving workload: the same open-loop trace replayed through the server
-    (continuous batching) and as one plain launch per request."""
+    (continuous batching) and as one plain launch per request, at the
+    configured rate and again at a saturating rate (where one host thread
+    can no longer launch every request on its own)."""
     import ctypes as C
 
     dev = torch.device("cuda:0")
@@ -157,8 +162,6 @@ def serve_bench(args, torch, mdt):
     dst = {f: torch.zeros(b, dtype=torch.uint8, device=dev) for f, b in arena.items()}
     pk_in = torch.from_numpy(inputs.random_bytes(64 << 20, seed=5)).to(dev)
     ring = torch.empty(4 << 30, dtype=torch.uint8, device=dev)
-    tr = inputs.serving_trace(args.rate, args.duration, len(types))
-    n = tr["t_us"].size
 
     class Req(C.Structure):
         _fields_ = [("t_arrive_us", C.c_double), ("unpack", C.c_int32), ("type_index", C.c_int32),
@@ -169,54 +172,86 @@ def serve_bench(args, torch, mdt):
         _fields_ = [("completed", C.c_int64), ("failed", C.c_int64), ("bytes", C.c_int64), ("elapsed_s", C.c_double),
                     ("p50_us", C.c_double), ("p99_us", C.c_double), ("max_us", C.c_double), ("mean_us", C.c_double),
                     ("launches", C.c_int64), ("late_issues", C.c_int64), ("p50_queue_us", C.c_double),
-                    ("p99_queue_us", C.c_double), ("p50_run_us", C.c_double), ("p99_run_us", C.c_double)]
+                    ("p99_queue_us", C.c_double), ("p50_run_us", C.c_double), ("p99_run_us", C.c_double),
+                    ("p50_issue_us", C.c_double), ("p99_issue_us", C.c_double)]
 
-    size = np.array([t.size() for t in types], np.int64)
-    ext = np.array([t.extent()[1] for t in types], np.int64)
-    tlb = np.array([t.true_extent()[0] for t in types], np.int64)
-    tex = np.array([t.true_extent()[1] for t in types], np.int64)
-    fam = [f for f, _ in fam_types]
-    reqs = (Req * n)()
-    truncated = 0
-    total_bytes = 0
-    slot = 64 << 20
-    for i in range(n):
-        ti = int(tr["type_index"][i])
-        want = int(tr["target"][i])
-        cnt = -(-want // int(size[ti]))
-        cap = 1 + (arena[fam[ti]] - int(tlb[ti]) - int(tex[ti])) // max(1, int(ext[ti]))
-        if cnt > cap:
-            cnt = cap
-            truncated += 1
-        tgt = min(want, cnt * int(size[ti]))
-        total_bytes += tgt
-        up = int(tr["unpack"][i])
-        r = reqs[i]
-        r.t_arrive_us = float(tr["t_us"][i])
-        r.unpack = up
-        r.type_index = ti
-        r.count = cnt
-        r.target = tgt
-        r.typed = (dst if up else src)[fam[ti]].data_ptr()
-        r.packed = pk_in.data_ptr()
-        r.out = ring.data_ptr() + (i % ((4 << 30) // slot)) * slot
-    handles = (C.c_void_p * len(types))(*[t.handle for t in types])
-    lg = C.CDLL(os.path.join(HERE, "paper_2402_12274_amd", "libmdt_loadgen.so"))
-    lg.mdt_lg_run_served.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.POINTER(mdt.ServerConfig), C.POINTER(Res)]
-    lg.mdt_lg_run_plain.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.POINTER(Res)]
-    cfg = mdt.ServerConfig(8, 32 << 30, 256, 2, 0)
-    torch.cuda.synchronize()
-    served, plain = Res(), Res()
-    mdt.check(lg.mdt_lg_run_served(reqs, n, handles, C.byref(cfg), C.byref(served)), "served run")
-    mdt.check(lg.mdt_lg_run_plain(reqs, n, handles, 8, C.byref(plain)), "per-request run")
-    torch.cuda.synchronize()
+    def replay(rate, duration):
+        """Replay one trace through the server and as per-request launches."""
+        tr = inputs.serving_trace(rate, duration, len(types))
+        n = tr["t_us"].size
+        size = np.array([t.size() for t in types], np.int64)
+        ext = np.array([t.extent()[1] for t in types], np.int64)
+        tlb = np.array([t.true_extent()[0] for t in types], np.int64)
+        tex = np.array([t.true_extent()[1] for t in types], np.int64)
+        fam = [f for f, _ in fam_types]
+        reqs = (Req * n)()
+        truncated = 0
+        total_bytes = 0
+        slot = 64 << 20
+        for i in range(n):
+            ti = int(tr["type_index"][i])
+            want = int(tr["target"][i])
+            cnt = -(-want // int(size[ti]))
+            cap = 1 + (arena[fam[ti]] - int(tlb[ti]) - int(tex[ti])) // max(1, int(ext[ti]))
+            if cnt > cap:
+                cnt = cap
+                truncated += 1
+            tgt = min(want, cnt * int(size[ti]))
+            total_bytes += tgt
+            up = int(tr["unpack"][i])
+            r = reqs[i]
+            r.t_arrive_us = float(tr["t_us"][i])
+            r.unpack = up
+            r.type_index = ti
+            r.count = cnt
+            r.target = tgt
+            r.typed = (dst if up else src)[fam[ti]].data_ptr()
+            r.packed = pk_in.data_ptr()
+            r.out = ring.data_ptr() + (i % ((4 << 30) // slot)) * slot
+        handles = (C.c_void_p * len(types))(*[t.handle for t in types])
+        lg = C.CDLL(os.path.join(HERE, "paper_2402_12274_amd", "libmdt_loadgen.so"))
+        dp = C.POINTER(C.c_double)
+        lg.mdt_lg_run_served.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.POINTER(mdt.ServerConfig), C.POINTER(Res),
+                                         dp]
+        lg.mdt_lg_run_plain.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.POINTER(Res), dp]
+        cfg = mdt.ServerConfig(8, 32 << 30, 256, 2, 0)
+        torch.cuda.synchronize()
+        served, plain = Res(), Res()
+        lat_s, lat_p = np.zeros(n), np.zeros(n)
+        mdt.check(lg.mdt_lg_run_served(reqs, n, handles, C.byref(cfg), C.byref(served), lat_s.ctypes.data_as(dp)),
+                  "served run")
+        mdt.check(lg.mdt_lg_run_plain(reqs, n, handles, 8, C.byref(plain), lat_p.ctypes.data_as(dp)), "per-request run")
+        torch.cuda.synchronize()
+        # latency by type family and by size class (both modes replay the same trace)
+        fam_of = np.array([fam[int(ti)] for ti in tr["type_index"]])
+        tgt_b = np.array([reqs[i].target for i in range(n)], np.int64)
+
+        def pct(lat, sel):
+            v = lat[sel & (lat >= 0)]
+            return [round(float(np.percentile(v, 50)), 1), round(float(np.percentile(v, 99)), 1), int(v.size)] if v.size \
+                else None
+
+        breakdown = {}
+        for key, sel in [(f, fam_of == f) for f in ("vector", "face", "hindexed", "struct")] + \
+                        [("<64KiB", tgt_b < (64 << 10)), ("64KiB-4MiB", (tgt_b >= (64 << 10)) & (tgt_b < (4 << 20))),
+                         (">=4MiB", tgt_b >= (4 << 20))]:
+            breakdown[key] = {"served_p50_p99_n": pct(lat_s, sel), "per_request_p50_p99_n": pct(lat_p, sel)}
+
+        return tr, n, served, plain, breakdown, truncated, total_bytes
 
     def summ(r):
         return {"completed": r.completed, "failed": r.failed, "GBps": round(2 * r.bytes / r.elapsed_s / 1e9, 2),
                 "p50_us": round(r.p50_us, 1), "p99_us": round(r.p99_us, 1), "max_us": round(r.max_us, 1),
                 "launches": r.launches, "late_issues": r.late_issues, "elapsed_s": round(r.elapsed_s, 3),
                 "server_p50_queue_us": round(r.p50_queue_us, 1), "server_p99_queue_us": round(r.p99_queue_us, 1),
-                "server_p50_run_us": round(r.p50_run_us, 1), "server_p99_run_us": round(r.p99_run_us, 1)}
+                "server_p50_run_us": round(r.p50_run_us, 1), "server_p99_run_us": round(r.p99_run_us, 1),
+                "p50_issue_us": round(r.p50_issue_us, 2), "p99_issue_us": round(r.p99_issue_us, 2)}
+
+    tr, n, served, plain, breakdown, truncated, total_bytes = replay(args.rate, args.duration)
+    sat = None
+    if args.sat_rate > 0:
+        _, n2, served2, plain2, _, _, _ = replay(args.sat_rate, args.sat_duration)
+        sat = (n2, served2, plain2)
 
     s_, p_ = summ(served), summ(plain)
     out = {
@@ -227,8 +262,11 @@ def serve_bench(args, torch, mdt):
                                "pack/unpack, sizes 256 B x Zipf(1.2) up to 64 MiB, 500 resident types, 8 streams, "
                                "32 GiB admission budget",
                    "requests": n, "offered_bytes": total_bytes, "truncated_requests": truncated},
-        "served": s_, "per_request": p_,
+        "served": s_, "per_request": p_, "latency_breakdown_us": breakdown,
     }
+    if sat is not None:
+        out["saturation"] = {"rate_per_s": args.sat_rate, "duration_s": args.sat_duration, "requests": sat[0],
+                             "served": summ(sat[1]), "per_request": summ(sat[2])}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -333,6 +371,7 @@ def main():
     step_bytes = 4 * sum(sizes)
 
     batches = None
+    tuned = None
     if args.mode == "batched":
         batches = []
         for r in range(R):
@@ -343,8 +382,7 @@ def main():
                 bu.add_unpack(out.data_ptr(), t.size() * count, dsts[r].data_ptr(), count, t, 0)
             batches.append((bp, bu))
         bp0, bu0 = batches[0]
-        bp0.autotune(ms)
-        bu0.autotune(ms)
+        tuned = {"pack": mdt.config_dict(bp0.autotune(ms)), "unpack": mdt.config_dict(bu0.autotune(ms))}
         for bp, bu in batches[1:]:
             bp.set_config(bp0.get_config())
             bu.set_config(bu0.get_config())
@@ -433,7 +471,7 @@ def main():
         "config": {"workload": W["desc"], "mode": args.mode, "requests_per_step": 2 * len(types),
                    "packed_bytes_per_step": sum(sizes), "rotating_copies": R,
                    "frac_of_peak_value": round(value / PEAK_HBM_GBS, 4),
-                   "device_copy_ceiling_GBps": copy_ceiling},
+                   "device_copy_ceiling_GBps": copy_ceiling, "autotuned": tuned},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
                      "kernel": dom,

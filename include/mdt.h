@@ -258,7 +258,7 @@ MDT_API int mdt_batch_add_unpack(mdt_batch b, const void *inbuf, mdt_count insiz
  * of tiles over workgroups, 1 = dynamic (atomic tile counter). */
 typedef struct mdt_batch_config {
     int tile_chunks;    /* 16-byte chunks per workgroup tile: 256, 512, 1024, 2048, 4096 */
-    int wgs_per_cu;     /* persistent workgroups per compute unit, 1..16 */
+    int wgs_per_cu;     /* persistent workgroups per compute unit, 1..16; 0: one workgroup per tile */
     int policy;         /* 0 static, 1 dynamic */
     int use_graph;      /* 1 = capture and replay a HIP graph, 0 = direct launches */
 } mdt_batch_config;

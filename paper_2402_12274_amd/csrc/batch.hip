@@ -37,11 +37,13 @@ struct ReqDesc {
     int32_t elem1, dense;
 };
 
+// Descriptors are stored pack requests first, so each direction's tiles
+// form one range: [0, ntiles_dir[0]) for pack, then unpack.
 struct BatchHeader {
-    int64_t nreq;
-    int64_t ntiles;
+    int64_t nreq_dir[2];    // requests per direction
+    int64_t ntiles_dir[2];  // tiles per direction
     int64_t tile_chunks;
-    int64_t pad;
+    int64_t pad[3];
 };
 
 // Chunks [c0, cend) of one request, with the single-request bodies.
@@ -93,9 +95,10 @@ __device__ __forceinline__ const DevLayout &const_layout(uint64_t addr)
     return *(const DevLayout *)(const __attribute__((address_space(4))) DevLayout *)(uintptr_t)addr;
 }
 
-// Persistent batch kernel.  POLICY 0: tile t = blockIdx.x + k * gridDim.x;
+// Batch kernel for one direction.  POLICY 0: tile t = blockIdx.x + k *
+// gridDim.x (with one workgroup per tile, each workgroup takes one tile);
 // POLICY 1: tiles taken from an atomic counter.  Every workgroup leaves the
-// loop once the tile index reaches ntiles.
+// loop once the tile index passes the direction's last tile.
 template <int POLICY, int UNPACK>
 __global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restrict__ H,
                                                     const ReqDesc *__restrict__ R,
@@ -104,43 +107,44 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restric
 {
     extern __shared__ __align__(16) uint8_t lds_dyn[];
     __shared__ int64_t s_t;
-    const int64_t ntiles = H->ntiles, T = H->tile_chunks, nreq = H->nreq;
+    const int64_t T = H->tile_chunks;
+    // this direction's requests [r0, r1) and tiles [t_begin, t_end)
+    const int64_t r0 = UNPACK ? H->nreq_dir[0] : 0, r1 = r0 + H->nreq_dir[UNPACK];
+    const int64_t t_begin = UNPACK ? H->ntiles_dir[0] : 0, t_end = t_begin + H->ntiles_dir[UNPACK];
     int64_t t;
     if (POLICY == 0) {
-        t = blockIdx.x;
+        t = t_begin + blockIdx.x;
     } else {
-        if (threadIdx.x == 0) s_t = (int64_t)atomicAdd(counter, 1ull);
+        if (threadIdx.x == 0) s_t = t_begin + (int64_t)atomicAdd(counter, 1ull);
         __syncthreads();
         t = uniform64(s_t);
     }
-    while (t < ntiles) {
+    while (t < t_end) {
         // request holding tile t: last r with tile0[r] <= t
-        int64_t lo = 0, hi = nreq - 1;
+        int64_t lo = r0, hi = r1 - 1;
         while (lo < hi) {
             int64_t mid = (lo + hi + 1) >> 1;
             if (tile0[mid] <= t) lo = mid; else hi = mid - 1;
         }
         const ReqDesc &D = R[lo];
-        if (D.unpack == UNPACK) {  // tiles of the other direction belong to its own launch
-            const DevLayout &L = const_layout(D.lay);
-            XferArgs A;
-            A.typed = D.typed;
-            A.packed = D.packed;
-            A.off = D.off;
-            A.nbytes = D.nbytes;
-            A.head = D.head;
-            A.nchunks = D.nchunks;
-            A.tile_chunks = T;
-            A.elem1 = D.elem1;
-            int64_t c0 = (t - tile0[lo]) * T;
-            int64_t cend = c0 + T < D.nchunks ? c0 + T : D.nchunks;
-            run_tile(L, A, UNPACK, D.dense, D.kind, c0, cend, lds_dyn);
-        }
+        const DevLayout &L = const_layout(D.lay);
+        XferArgs A;
+        A.typed = D.typed;
+        A.packed = D.packed;
+        A.off = D.off;
+        A.nbytes = D.nbytes;
+        A.head = D.head;
+        A.nchunks = D.nchunks;
+        A.tile_chunks = T;
+        A.elem1 = D.elem1;
+        int64_t c0 = (t - tile0[lo]) * T;
+        int64_t cend = c0 + T < D.nchunks ? c0 + T : D.nchunks;
+        run_tile(L, A, UNPACK, D.dense, D.kind, c0, cend, lds_dyn);
         if (POLICY == 0) {
             t += gridDim.x;
         } else {
             __syncthreads();
-            if (threadIdx.x == 0) s_t = (int64_t)atomicAdd(counter, 1ull);
+            if (threadIdx.x == 0) s_t = t_begin + (int64_t)atomicAdd(counter, 1ull);
             __syncthreads();
             t = uniform64(s_t);
         }
@@ -171,14 +175,15 @@ struct mdt_batch_s {
     size_t cap = 0;  // requests the buffer holds
     uint8_t *h_stage = nullptr;  // pinned staging of the same layout
     hipEvent_t staged = nullptr; // the last upload from h_stage has been consumed
-    unsigned long long *d_counter = nullptr;
-    int64_t ntiles = 0;
+    unsigned long long *d_counter = nullptr;  // [2] tile counters, one per direction
+    int64_t ntiles_dir[2] = {0, 0};
     int32_t lds = 0;  // dynamic LDS of the persistent kernel (largest dense request)
     int32_t dirs = 0; // bit 0: has pack requests, bit 1: has unpack requests
     // captured launch
     hipGraphExec_t exec = nullptr;
     hipStream_t cap_stream = nullptr;
-    int graph_grid = -1, graph_policy = -1, graph_lds = -1;
+    int graph_grid[2] = {-1, -1};
+    int graph_policy = -1, graph_lds = -1;
     uint8_t *graph_buf = nullptr;
 };
 
@@ -193,7 +198,7 @@ void release_graph(mdt_batch_s *b)
 {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     b->exec = nullptr;
-    b->graph_grid = b->graph_policy = -1;
+    b->graph_grid[0] = b->graph_grid[1] = b->graph_policy = -1;
 }
 
 int ensure_capacity(mdt_batch_s *b, size_t n)
@@ -236,7 +241,7 @@ int init_device(mdt_batch_s *b)
     b->device = dev;
     if (hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || b->ncu <= 0)
         b->ncu = 256;
-    if (hipMalloc((void **)&b->d_counter, sizeof(unsigned long long)) != hipSuccess) return MDT_ERR_NO_MEM;
+    if (hipMalloc((void **)&b->d_counter, 2 * sizeof(unsigned long long)) != hipSuccess) return MDT_ERR_NO_MEM;
     if (hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) return MDT_ERR_HIP;
     if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) return MDT_ERR_HIP;
     return MDT_SUCCESS;
@@ -256,24 +261,31 @@ int stage(mdt_batch_s *b, hipStream_t s)
     }
     const int64_t T = b->cfg.tile_chunks;
     BatchHeader H{};
-    H.nreq = (int64_t)b->reqs.size();
     H.tile_chunks = T;
     ReqDesc *D = (ReqDesc *)(b->h_stage + desc_off());
     int64_t *tile0 = (int64_t *)(b->h_stage + tile_off(b->cap));
     int64_t acc = 0;
+    size_t k = 0;
     b->lds = 0;
     b->dirs = 0;
-    for (size_t i = 0; i < b->reqs.size(); i++) {
-        D[i] = b->reqs[i].d;
-        if (D[i].dense) b->lds = std::max(b->lds, b->reqs[i].lds);
-        b->dirs |= D[i].unpack ? 2 : 1;
-        tile0[i] = acc;
-        acc += (b->reqs[i].d.nchunks + T - 1) / T;
+    // pack requests first, then unpack, each in the order they were added
+    for (int dir = 0; dir < 2; dir++) {
+        const int64_t acc0 = acc;
+        for (size_t i = 0; i < b->reqs.size(); i++) {
+            if (b->reqs[i].d.unpack != dir) continue;
+            D[k] = b->reqs[i].d;
+            if (D[k].dense) b->lds = std::max(b->lds, b->reqs[i].lds);
+            tile0[k] = acc;
+            acc += (b->reqs[i].d.nchunks + T - 1) / T;
+            H.nreq_dir[dir]++;
+            k++;
+        }
+        H.ntiles_dir[dir] = acc - acc0;
+        b->ntiles_dir[dir] = acc - acc0;
+        if (acc > acc0) b->dirs |= 1 << dir;
     }
-    tile0[b->reqs.size()] = acc;
-    H.ntiles = acc;
+    tile0[k] = acc;
     std::memcpy(b->h_stage, &H, sizeof H);
-    b->ntiles = acc;
     size_t n = tile_off(b->cap) + (b->reqs.size() + 1) * sizeof(int64_t);
     e = hipMemcpyAsync(b->d_buf, b->h_stage, n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipEventRecord(b->staged, s);
@@ -285,14 +297,16 @@ int stage(mdt_batch_s *b, hipStream_t s)
     return MDT_SUCCESS;
 }
 
-int grid_of(const mdt_batch_s *b)
+// Workgroups of one direction's launch: wgs_per_cu per compute unit
+// (persistent), or one per tile when wgs_per_cu is 0.
+int grid_of(const mdt_batch_s *b, int dir)
 {
-    int64_t g = (int64_t)b->ncu * std::max(1, b->cfg.wgs_per_cu);
-    if (g > b->ntiles) g = b->ntiles;
-    return (int)std::max<int64_t>(1, g);
+    const int64_t n = b->ntiles_dir[dir];
+    int64_t g = b->cfg.wgs_per_cu > 0 ? std::min<int64_t>((int64_t)b->ncu * b->cfg.wgs_per_cu, n) : n;
+    return (int)std::min<int64_t>(std::max<int64_t>(1, g), INT32_MAX);
 }
 
-void enqueue_kernels(mdt_batch_s *b, hipStream_t s, int grid)
+void enqueue_kernels(mdt_batch_s *b, hipStream_t s)
 {
     const BatchHeader *H = (const BatchHeader *)b->d_buf;
     const ReqDesc *R = (const ReqDesc *)(b->d_buf + desc_off());
@@ -301,13 +315,15 @@ void enqueue_kernels(mdt_batch_s *b, hipStream_t s, int grid)
     // unpack tiles as two launches (each kernel skips the other direction)
     for (int dir = 0; dir < 2; dir++) {
         if (!(b->dirs & (1 << dir))) continue;
+        const dim3 grid((unsigned)grid_of(b, dir));
+        unsigned long long *ctr = b->d_counter + dir;
         if (b->cfg.policy == 1) {
-            hipLaunchKernelGGL(batch_counter_reset, dim3(1), dim3(1), 0, s, b->d_counter);
-            if (dir) hipLaunchKernelGGL((batch_kernel<1, 1>), dim3(grid), dim3(256), (size_t)b->lds, s, H, R, tile0, b->d_counter);
-            else hipLaunchKernelGGL((batch_kernel<1, 0>), dim3(grid), dim3(256), (size_t)b->lds, s, H, R, tile0, b->d_counter);
+            hipLaunchKernelGGL(batch_counter_reset, dim3(1), dim3(1), 0, s, ctr);
+            if (dir) hipLaunchKernelGGL((batch_kernel<1, 1>), grid, dim3(256), (size_t)b->lds, s, H, R, tile0, ctr);
+            else hipLaunchKernelGGL((batch_kernel<1, 0>), grid, dim3(256), (size_t)b->lds, s, H, R, tile0, ctr);
         } else {
-            if (dir) hipLaunchKernelGGL((batch_kernel<0, 1>), dim3(grid), dim3(256), (size_t)b->lds, s, H, R, tile0, b->d_counter);
-            else hipLaunchKernelGGL((batch_kernel<0, 0>), dim3(grid), dim3(256), (size_t)b->lds, s, H, R, tile0, b->d_counter);
+            if (dir) hipLaunchKernelGGL((batch_kernel<0, 1>), grid, dim3(256), (size_t)b->lds, s, H, R, tile0, ctr);
+            else hipLaunchKernelGGL((batch_kernel<0, 0>), grid, dim3(256), (size_t)b->lds, s, H, R, tile0, ctr);
         }
     }
 }
@@ -318,10 +334,10 @@ int launch(mdt_batch_s *b, hipStream_t s)
     if (rc) return rc;
     rc = stage(b, s);
     if (rc) return rc;
-    if (b->ntiles == 0) return MDT_SUCCESS;
-    int grid = grid_of(b);
+    if (b->ntiles_dir[0] + b->ntiles_dir[1] == 0) return MDT_SUCCESS;
+    const int g0 = (b->dirs & 1) ? grid_of(b, 0) : 0, g1 = (b->dirs & 2) ? grid_of(b, 1) : 0;
     if (!b->cfg.use_graph) {
-        enqueue_kernels(b, s, grid);
+        enqueue_kernels(b, s);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) {
             set_hip_error((int)e);
@@ -329,13 +345,13 @@ int launch(mdt_batch_s *b, hipStream_t s)
         }
         return MDT_SUCCESS;
     }
-    if (!b->exec || b->graph_grid != grid || b->graph_policy != b->cfg.policy || b->graph_buf != b->d_buf ||
-        b->graph_lds != b->lds) {
+    if (!b->exec || b->graph_grid[0] != g0 || b->graph_grid[1] != g1 || b->graph_policy != b->cfg.policy ||
+        b->graph_buf != b->d_buf || b->graph_lds != b->lds) {
         release_graph(b);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            enqueue_kernels(b, b->cap_stream, grid);
+            enqueue_kernels(b, b->cap_stream);
             e = hipStreamEndCapture(b->cap_stream, &g);
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
@@ -345,7 +361,8 @@ int launch(mdt_batch_s *b, hipStream_t s)
             b->exec = nullptr;
             return MDT_ERR_HIP;
         }
-        b->graph_grid = grid;
+        b->graph_grid[0] = g0;
+        b->graph_grid[1] = g1;
         b->graph_policy = b->cfg.policy;
         b->graph_lds = b->lds;
         b->graph_buf = b->d_buf;
@@ -364,7 +381,7 @@ bool valid_cfg(const mdt_batch_config &c)
 {
     bool tc = c.tile_chunks == 256 || c.tile_chunks == 512 || c.tile_chunks == 1024 || c.tile_chunks == 2048 ||
               c.tile_chunks == 4096;
-    return tc && c.wgs_per_cu >= 1 && c.wgs_per_cu <= 16 && (c.policy == 0 || c.policy == 1) &&
+    return tc && c.wgs_per_cu >= 0 && c.wgs_per_cu <= 16 && (c.policy == 0 || c.policy == 1) &&
            (c.use_graph == 0 || c.use_graph == 1);
 }
 
@@ -507,11 +524,12 @@ MDT_API int mdt_batch_autotune(mdt_batch b, mdt_stream s, mdt_batch_config *best
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MDT_ERR_HIP;
     const int tiles[] = {256, 1024, 4096};
-    const int occ[] = {2, 4, 8};
+    const int occ[] = {0, 2, 4, 8};  // 0: one workgroup per tile
     int rc = MDT_SUCCESS;
     for (int policy = 0; policy < 2 && !rc; policy++)
         for (int tc : tiles)
             for (int w : occ) {
+                if (policy == 1 && w == 0) continue;  // nothing to balance with a workgroup per tile
                 mdt_batch_config c{tc, w, policy, keep.use_graph};
                 mdt_batch_set_config(b, &c);
                 rc = launch(b, s->s);  // warm-up (uploads, graph capture)

@@ -45,6 +45,7 @@ struct mdt_lg_result {
     int64_t launches;
     int64_t late_issues;  // requests issued more than 50 us after their scheduled time
     double p50_queue_us, p99_queue_us, p50_run_us, p99_run_us;  // served: server-side split
+    double p50_issue_us, p99_issue_us;  // duration of the submit / enqueue call
 };
 
 }  // extern "C"
@@ -55,6 +56,23 @@ double now_us()
 {
     using namespace std::chrono;
     return (double)duration_cast<nanoseconds>(steady_clock::now().time_since_epoch()).count() * 1e-3;
+}
+
+// Between arrivals the issuing thread polls: a timed sleep on Linux lasts
+// tens of microseconds longer than asked (timer slack), which would show up
+// as latency of whatever completes meanwhile.  It sleeps only when the next
+// arrival is more than a millisecond away, and wakes well before it.
+void wait_for_next(double t_next)
+{
+    const double gap = t_next - now_us();
+    if (gap > 1000.0) std::this_thread::sleep_for(std::chrono::microseconds((int64_t)(gap - 500.0)));
+}
+
+double pctl(std::vector<double> v, double f)
+{
+    if (v.empty()) return 0.0;
+    std::sort(v.begin(), v.end());
+    return v[std::min(v.size() - 1, (size_t)(f * (double)(v.size() - 1) + 0.5))];
 }
 
 void summarize(std::vector<double> &lat, mdt_lg_result *r)
@@ -76,10 +94,14 @@ extern "C" {
 
 // Serve the trace through an mdt_server (progress thread on).  Pack outputs
 // live in the server's arena and are released as soon as they complete.
+// lat_out (optional, n entries): each request's latency in us, -1 if it failed.
 __attribute__((visibility("default"))) int mdt_lg_run_served(const mdt_lg_req *reqs, int64_t n, const mdt_type *types,
-                                                             const mdt_server_config *cfg, mdt_lg_result *res)
+                                                             const mdt_server_config *cfg, mdt_lg_result *res,
+                                                             double *lat_out)
 {
     std::memset(res, 0, sizeof *res);
+    if (lat_out)
+        for (int64_t k = 0; k < n; k++) lat_out[k] = -1.0;
     mdt_server srv = nullptr;
     int rc = mdt_server_create(cfg, &srv);
     if (rc) return rc;
@@ -91,10 +113,12 @@ __attribute__((visibility("default"))) int mdt_lg_run_served(const mdt_lg_req *r
     struct Pending {
         mdt_request r;
         double t_arrive;
+        int64_t idx;
     };
     std::deque<Pending> pend;
-    std::vector<double> lat;
+    std::vector<double> lat, issue;
     lat.reserve((size_t)n);
+    issue.reserve((size_t)n);
     const double t0 = now_us() + 1000.0;
     double last_done = t0;
     int64_t i = 0;
@@ -117,6 +141,7 @@ __attribute__((visibility("default"))) int mdt_lg_run_served(const mdt_lg_req *r
                     res->completed++;
                     res->bytes += nb;
                     lat.push_back(t - pend[k].t_arrive);
+                    if (lat_out) lat_out[pend[k].idx] = t - pend[k].t_arrive;
                 } else {
                     res->failed++;
                 }
@@ -135,18 +160,20 @@ __attribute__((visibility("default"))) int mdt_lg_run_served(const mdt_lg_req *r
             const mdt_lg_req &q = reqs[i];
             mdt_request r = nullptr;
             int e;
+            const double ti = now_us();
             if (q.unpack)
                 e = mdt_server_submit_unpack(srv, q.packed, q.target, const_cast<void *>(q.typed), q.count,
                                              types[q.type_index], 0, &r);
             else
                 e = mdt_server_submit_pack(srv, q.typed, q.count, types[q.type_index], 0, q.target, &r);
+            issue.push_back(now_us() - ti);
             if (t - (t0 + q.t_arrive_us) > 50.0) res->late_issues++;
             if (e) res->failed++;
-            else pend.push_back({r, t0 + q.t_arrive_us});
+            else pend.push_back({r, t0 + q.t_arrive_us, i});
             i++;
         }
         reap(false);
-        if (i < n && t0 + reqs[i].t_arrive_us > now_us() + 20.0) std::this_thread::sleep_for(std::chrono::microseconds(5));
+        wait_for_next(i < n ? t0 + reqs[i].t_arrive_us : 0.0);
     }
     mdt_server_stats st{};
     mdt_server_stats_get(srv, &st);
@@ -158,14 +185,18 @@ __attribute__((visibility("default"))) int mdt_lg_run_served(const mdt_lg_req *r
     mdt_server_free(&srv);
     res->elapsed_s = (last_done - t0) * 1e-6;
     summarize(lat, res);
+    res->p50_issue_us = pctl(issue, 0.50);
+    res->p99_issue_us = pctl(issue, 0.99);
     return MDT_SUCCESS;
 }
 
 // One plain launch per request on stream (index mod nstreams).
 __attribute__((visibility("default"))) int mdt_lg_run_plain(const mdt_lg_req *reqs, int64_t n, const mdt_type *types,
-                                                            int nstreams, mdt_lg_result *res)
+                                                            int nstreams, mdt_lg_result *res, double *lat_out)
 {
     std::memset(res, 0, sizeof *res);
+    if (lat_out)
+        for (int64_t k = 0; k < n; k++) lat_out[k] = -1.0;
     std::vector<hipStream_t> hs((size_t)nstreams);
     std::vector<mdt_stream> ms((size_t)nstreams);
     for (int s = 0; s < nstreams; s++) {
@@ -176,12 +207,14 @@ __attribute__((visibility("default"))) int mdt_lg_run_plain(const mdt_lg_req *re
         mdt_request r;
         double t_arrive;
         int64_t bytes;
+        int64_t idx;
     };
     // requests on one stream complete in order: poll only each stream's oldest
     std::vector<std::deque<Pending>> pend((size_t)nstreams);
     int64_t npend = 0;
-    std::vector<double> lat;
+    std::vector<double> lat, issue;
     lat.reserve((size_t)n);
+    issue.reserve((size_t)n);
     const double t0 = now_us() + 1000.0;
     double last_done = t0;
     int64_t i = 0;
@@ -193,15 +226,17 @@ __attribute__((visibility("default"))) int mdt_lg_run_plain(const mdt_lg_req *re
             int64_t got = 0;
             mdt_stream s = ms[(size_t)(i % nstreams)];
             int e;
+            const double ti = now_us();
             if (q.unpack)
                 e = mdt_unpack_enqueue(q.packed, q.target, const_cast<void *>(q.typed), q.count, types[q.type_index], 0,
                                        &got, s, &r);
             else
                 e = mdt_pack_enqueue(q.typed, q.count, types[q.type_index], 0, q.out, q.target, &got, s, &r);
+            issue.push_back(now_us() - ti);
             if (t - (t0 + q.t_arrive_us) > 50.0) res->late_issues++;
             if (e) res->failed++;
             else {
-                pend[(size_t)(i % nstreams)].push_back({r, t0 + q.t_arrive_us, got});
+                pend[(size_t)(i % nstreams)].push_back({r, t0 + q.t_arrive_us, got, i});
                 npend++;
                 res->launches++;
             }
@@ -216,12 +251,13 @@ __attribute__((visibility("default"))) int mdt_lg_run_plain(const mdt_lg_req *re
                 res->completed++;
                 res->bytes += dq.front().bytes;
                 lat.push_back(tc - dq.front().t_arrive);
+                if (lat_out) lat_out[dq.front().idx] = tc - dq.front().t_arrive;
                 last_done = std::max(last_done, tc);
                 dq.pop_front();
                 npend--;
             }
         }
-        if (i < n && t0 + reqs[i].t_arrive_us > now_us() + 20.0) std::this_thread::sleep_for(std::chrono::microseconds(5));
+        wait_for_next(i < n ? t0 + reqs[i].t_arrive_us : 0.0);
     }
     for (int s = 0; s < nstreams; s++) {
         (void)hipStreamSynchronize(hs[s]);
@@ -230,6 +266,8 @@ __attribute__((visibility("default"))) int mdt_lg_run_plain(const mdt_lg_req *re
     }
     res->elapsed_s = (last_done - t0) * 1e-6;
     summarize(lat, res);
+    res->p50_issue_us = pctl(issue, 0.50);
+    res->p99_issue_us = pctl(issue, 0.99);
     return MDT_SUCCESS;
 }
 

@@ -1,24 +1,28 @@
 // server.cpp -- continuous-batching progress engine for pack/unpack requests.
 //
-// Clients submit requests from any thread (a short locked queue); a progress
-// round (MPIX_Stream_progress in the General Progress section; run by the
-// caller or by a progress thread, MPIX_Start_progress_thread) does three
-// things:
-//   1. reap: query the completion event of every launch in flight and
-//      complete its requests (the poll-callback pattern of generalized
-//      requests: query the event, complete the request), stamping latency;
+// Clients submit requests from any thread; every submit, and a progress
+// thread while work is outstanding (MPIX_Stream_progress and
+// MPIX_Start_progress_thread in the General Progress section), run progress
+// rounds.  A round does three things:
+//   0. take back what released requests held (arena range, budget charge);
+//   1. reap: query the completion event of the oldest launch of each stream
+//      (a stream finishes in order) and complete its requests (the
+//      poll-callback pattern of generalized requests), stamping latency;
 //   2. admit: move queued requests into the admitted set while the bytes
 //      they hold (packed buffer, plus the destination span for unpack) fit
 //      in the memory budget -- requests that do not fit wait, they do not
 //      fail; pack outputs come from a device arena allocated once, so the
 //      loop never calls hipMalloc;
-//   3. launch: while some stream has a free launch slot, cut up to max_batch
-//      admitted requests into one batched persistent launch on the least
-//      loaded stream and record its completion event.
-// Requests arriving while others run are admitted as soon as slots and
-// memory free up, so their work overlaps on the device.  Each request's bytes
-// are those of the same request run alone (the batch runs the single-request
-// chunk bodies).
+//   3. launch: while some stream has a free launch slot, cut admitted
+//      requests (up to max_batch, and up to a byte cap so small requests are
+//      not held behind a large one) into one launch on the stream with the
+//      least work in flight: a lone request with the single-request kernels,
+//      several as one batched launch; record its completion event.
+// A submit runs a round itself, so a request that can be admitted is
+// launched before submit returns; requests that arrive while others run are
+// admitted as soon as slots and memory free up, and their work overlaps on
+// the device.  Each request's bytes are those of the same request run alone
+// (the batch runs the single-request tile bodies).
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -59,9 +63,22 @@ const int64_t BATCH_BYTES = [] {
     long long v = e && *e ? atoll(e) : (8ll << 20);
     return (int64_t)(v > 0 ? v : (8ll << 20));
 }();
+// Hardware queues a process's streams are spread over (the runtime's
+// GPU_MAX_HW_QUEUES, 4 unless set).
+const int HW_QUEUES = [] {
+    const char *e = getenv("GPU_MAX_HW_QUEUES");
+    int v = e && *e ? atoi(e) : 4;
+    return v >= 1 && v <= 64 ? v : 4;
+}();
 // The progress thread keeps polling for this long after the last activity
 // before it sleeps (a sleeping thread wakes with scheduler latency).
 constexpr double SPIN_US = 2000.0;
+// Completion queries: a client's test reaps at most this often; the
+// progress thread, which does not wait on requests itself, reaps launches
+// that only need completing at a slower cadence (so it rarely contends with
+// clients for the runtime).
+constexpr double TEST_REAP_US = 1.0;
+constexpr double THREAD_REAP_US = 20.0;
 
 double now_us()
 {
@@ -84,42 +101,72 @@ struct Item {
     bool deferred = false;
 };
 
-// first-fit allocator over one device allocation
+// Allocator over one device allocation: free ranges indexed by offset (for
+// coalescing) and by length (best fit in O(log n), so a fragmented arena
+// does not make every admission scan the free list).
 struct Arena {
     uint8_t *base = nullptr;
     int64_t size = 0;
-    std::map<int64_t, int64_t> free_;  // offset -> length
-    int64_t alloc(int64_t n)
+    std::map<int64_t, int64_t> free_;                  // offset -> length
+    std::multimap<int64_t, int64_t> by_len;            // length -> offset
+    static int64_t round(int64_t n)
     {
         n = (n + ARENA_ALIGN - 1) / ARENA_ALIGN * ARENA_ALIGN;
-        if (n == 0) n = ARENA_ALIGN;
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= n) {
-                int64_t off = it->first, len = it->second;
-                free_.erase(it);
-                if (len > n) free_[off + n] = len - n;
-                return off;
+        return n == 0 ? ARENA_ALIGN : n;
+    }
+    void add_free(int64_t off, int64_t len)
+    {
+        free_[off] = len;
+        by_len.emplace(len, off);
+    }
+    void drop_free(int64_t off, int64_t len)
+    {
+        free_.erase(off);
+        auto r = by_len.equal_range(len);
+        for (auto it = r.first; it != r.second; ++it)
+            if (it->second == off) {
+                by_len.erase(it);
+                break;
             }
-        }
-        return -1;
+    }
+    void init(uint8_t *b, int64_t n)
+    {
+        base = b;
+        size = n;
+        free_.clear();
+        by_len.clear();
+        add_free(0, n);
+    }
+    int64_t alloc(int64_t n)
+    {
+        n = round(n);
+        auto it = by_len.lower_bound(n);
+        if (it == by_len.end()) return -1;
+        const int64_t len = it->first, off = it->second;
+        drop_free(off, len);
+        if (len > n) add_free(off + n, len - n);
+        return off;
     }
     void release(int64_t off, int64_t n)
     {
-        n = (n + ARENA_ALIGN - 1) / ARENA_ALIGN * ARENA_ALIGN;
-        if (n == 0) n = ARENA_ALIGN;
-        auto it = free_.emplace(off, n).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
+        n = round(n);
+        auto nx = free_.lower_bound(off);
+        if (nx != free_.end() && off + n == nx->first) {
+            const int64_t l = nx->second;
+            drop_free(nx->first, l);
+            n += l;
         }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
+        auto pv = free_.lower_bound(off);
+        if (pv != free_.begin()) {
+            --pv;
+            if (pv->first + pv->second == off) {
+                const int64_t po = pv->first, pl = pv->second;
+                drop_free(po, pl);
+                off = po;
+                n += pl;
             }
         }
+        add_free(off, n);
     }
 };
 
@@ -128,7 +175,8 @@ struct Slot {
     hipEvent_t ev = nullptr;
     std::vector<Item *> items;
     bool busy = false;
-    uint64_t seq = 0;  // launch order on its stream
+    uint64_t seq = 0;    // launch order on its stream
+    int64_t bytes = 0;   // packed bytes of the launch
 };
 
 struct StreamState {
@@ -136,6 +184,7 @@ struct StreamState {
     std::vector<Slot> slots;
     int busy = 0;
     uint64_t next_seq = 0;
+    int64_t bytes = 0;  // packed bytes of the launches in flight
 };
 
 }  // namespace
@@ -146,15 +195,18 @@ struct mdt_server_s {
     int device = -1;
     std::vector<StreamState> streams;
     Arena arena;
-    std::mutex qmu;              // submit queue
+    std::mutex qmu;              // submit queue, released items, submit counters
     std::deque<Item *> queue;
+    std::vector<Item *> released;  // completed items the client let go of
     std::mutex mu;               // everything below; held by a progress round
     std::deque<Item *> admitted;
     int64_t inflight = 0, peak_inflight = 0;
     int inject_fail = 0;
     std::atomic<bool> run_thread{false};
     bool draining = false;       // shutdown: admit regardless of the budget
-    std::atomic<bool> light{true};  // few launches in flight: submitters may dispatch
+    std::atomic<int64_t> work{0};   // queued + admitted + released items + launches in flight
+    std::atomic<int> launches_inflight{0};
+    std::atomic<double> last_reap{0.0};  // time of the last completion query round
     std::condition_variable wake;  // submit -> idle progress thread
     std::thread th;
     // stats
@@ -186,33 +238,103 @@ void complete(mdt_server s, Item *it, int status, double t)
     it->state.store(3, std::memory_order_release);
 }
 
-// one progress round; caller holds s->mu
+// Return the arena range and budget charge of items the client released;
+// caller holds s->mu and s->qmu.
+void take_back_released(mdt_server s)
+{
+    for (Item *it : s->released) {
+        if (it->arena_off >= 0) s->arena.release(it->arena_off, std::max<int64_t>(it->nbytes, 1));
+        // admitted requests hold their charge until released
+        if (it->arena_off >= 0 || it->unpack) s->inflight -= it->charge;
+        release(it->type);
+        delete it;
+    }
+    s->released.clear();
+}
+
+Slot *oldest_busy(StreamState &st)
+{
+    Slot *old = nullptr;
+    for (auto &x : st.slots)
+        if (x.busy && (!old || x.seq < old->seq)) old = &x;
+    return old;
+}
+
+// complete the requests of a finished launch; caller holds s->mu
+void retire(mdt_server s, StreamState &st, Slot &sl, hipError_t e)
+{
+    double t = now_us();
+    int status = e == hipSuccess ? MDT_SUCCESS : MDT_ERR_HIP;
+    if (e != hipSuccess) set_hip_error((int)e);
+    for (Item *it : sl.items) complete(s, it, status, t);
+    sl.items.clear();
+    sl.busy = false;
+    st.busy--;
+    st.bytes -= sl.bytes;
+    sl.bytes = 0;
+    s->launches_inflight.fetch_sub(1, std::memory_order_relaxed);
+}
+
+// Reap under the lock: a stream finishes its launches in order, so only its
+// oldest running launch is queried.  Caller holds s->mu.
+void reap_locked(mdt_server s)
+{
+    s->last_reap.store(now_us(), std::memory_order_relaxed);
+    for (auto &st : s->streams) {
+        for (;;) {
+            Slot *old = oldest_busy(st);
+            if (!old) break;
+            hipError_t e = hipEventQuery(old->ev);
+            if (e == hipErrorNotReady) break;
+            retire(s, st, *old, e);
+        }
+    }
+}
+
+// Reap from the progress thread: the events are queried with the lock
+// released (a submitter is not held up by the queries); only this thread
+// retires launches while it runs, so the snapshot stays valid.
+bool reap_unlocked(mdt_server s)
+{
+    struct Cand {
+        StreamState *st;
+        Slot *sl;
+        uint64_t seq;
+        hipEvent_t ev;
+        hipError_t e;
+    };
+    Cand c[64];
+    int nc = 0;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        for (auto &st : s->streams) {
+            Slot *old = oldest_busy(st);
+            if (old && nc < 64) c[nc++] = {&st, old, old->seq, old->ev, hipSuccess};
+        }
+    }
+    bool any = false;
+    for (int k = 0; k < nc; k++) {
+        c[k].e = hipEventQuery(c[k].ev);
+        any = any || c[k].e != hipErrorNotReady;
+    }
+    s->last_reap.store(now_us(), std::memory_order_relaxed);
+    if (!any) return false;
+    std::lock_guard<std::mutex> g(s->mu);
+    for (int k = 0; k < nc; k++)
+        if (c[k].e != hipErrorNotReady && c[k].sl->busy && c[k].sl->seq == c[k].seq)
+            retire(s, *c[k].st, *c[k].sl, c[k].e);
+    return true;
+}
+
+// Admit and launch; caller holds s->mu.
 int progress_locked(mdt_server s)
 {
     int rc = MDT_SUCCESS;
-    // 1. reap completed launches; a stream finishes its launches in order, so
-    // only its oldest running launch is queried
-    for (auto &st : s->streams) {
-        for (;;) {
-            Slot *old = nullptr;
-            for (auto &x : st.slots)
-                if (x.busy && (!old || x.seq < old->seq)) old = &x;
-            if (!old) break;
-            Slot &sl = *old;
-            hipError_t e = hipEventQuery(sl.ev);
-            if (e == hipErrorNotReady) break;
-            double t = now_us();
-            int status = e == hipSuccess ? MDT_SUCCESS : MDT_ERR_HIP;
-            if (e != hipSuccess) set_hip_error((int)e);
-            for (Item *it : sl.items) complete(s, it, status, t);
-            sl.items.clear();
-            sl.busy = false;
-            st.busy--;
-        }
-    }
-    // 2. admit queued requests within the budget
+    // 2. return what released items held, then admit queued requests within
+    // the budget
     {
         std::lock_guard<std::mutex> q(s->qmu);
+        take_back_released(s);
         while (!s->queue.empty()) {
             Item *it = s->queue.front();
             if (!s->draining && s->inflight + it->charge > s->cfg.budget_bytes && s->inflight > 0) {
@@ -257,9 +379,25 @@ int progress_locked(mdt_server s)
     }
     // 3. launch batches on free slots, least-loaded stream first
     while (!s->admitted.empty()) {
+        // the stream with a free slot and the least work queued ahead of it
+        // on its hardware queue (streams are spread over the process's
+        // hardware queues in creation order, so streams i and i + k*HWQ share
+        // one, and its work runs in order)
+        const int nst = (int)s->streams.size();
+        const int hwq = std::max(1, std::min(nst, HW_QUEUES));
+        int64_t qbytes[64] = {0};
+        for (int i = 0; i < nst; i++) qbytes[i % hwq] += s->streams[(size_t)i].bytes;
         StreamState *best = nullptr;
-        for (auto &st : s->streams)
-            if (st.busy < (int)st.slots.size() && (!best || st.busy < best->busy)) best = &st;
+        int64_t best_load = 0;
+        for (int i = 0; i < nst; i++) {
+            StreamState &st = s->streams[(size_t)i];
+            if (st.busy >= (int)st.slots.size()) continue;
+            const int64_t load = qbytes[i % hwq];
+            if (!best || load < best_load || (load == best_load && st.busy < best->busy)) {
+                best = &st;
+                best_load = load;
+            }
+        }
         if (!best) break;
         Slot *sl = nullptr;
         for (auto &x : best->slots)
@@ -296,8 +434,11 @@ int progress_locked(mdt_server s)
             sl->items.push_back(it);
             sl->busy = true;
             sl->seq = best->next_seq++;
+            sl->bytes = it->nbytes;
             best->busy++;
+            best->bytes += sl->bytes;
             s->launches++;
+            s->launches_inflight.fetch_add(1, std::memory_order_relaxed);
             continue;
         }
         mdt_batch_clear(sl->batch);
@@ -338,49 +479,65 @@ int progress_locked(mdt_server s)
         }
         sl->busy = true;
         sl->seq = best->next_seq++;
+        sl->bytes = bytes;
         best->busy++;
+        best->bytes += bytes;
         s->launches++;
+        s->launches_inflight.fetch_add(1, std::memory_order_relaxed);
     }
     int inflight = 0;
     for (auto &st : s->streams) inflight += st.busy;
-    s->light.store(inflight < (int)s->streams.size() && s->admitted.empty(), std::memory_order_relaxed);
+    {
+        // stored under qmu: a later submit or release adds to this value
+        std::lock_guard<std::mutex> q(s->qmu);
+        s->work.store((int64_t)(s->queue.size() + s->released.size() + s->admitted.size()) + inflight,
+                      std::memory_order_release);
+    }
     return rc;
 }
 
+// a progress round from a caller: reaps unless the progress thread does
 int progress(mdt_server s)
 {
     std::lock_guard<std::mutex> g(s->mu);
+    if (!s->run_thread.load(std::memory_order_acquire)) reap_locked(s);
     return progress_locked(s);
 }
 
-// The progress thread polls continuously while anything is queued,
-// admitted or in flight, and sleeps on a condition variable (woken by
-// submit) when the server is idle.
+// The progress thread runs launching rounds while anything is queued,
+// admitted or released; while launches are only in flight it reaps them at a
+// slow cadence (clients testing their requests reap too); when idle it spins
+// for a while, then sleeps on a condition variable until a submit wakes it.
 void thread_main(mdt_server s)
 {
     (void)hipSetDevice(s->device);
     double last_active = now_us();
     while (s->run_thread.load(std::memory_order_acquire)) {
-        bool idle;
-        {
-            std::lock_guard<std::mutex> g(s->mu);
-            progress_locked(s);
-            bool busy = !s->admitted.empty();
-            for (auto &st : s->streams) busy = busy || st.busy > 0;
-            std::lock_guard<std::mutex> q(s->qmu);
-            idle = !busy && s->queue.empty();
-        }
-        double t = now_us();
-        if (!idle) last_active = t;
-        if (!idle || t - last_active < SPIN_US) {
-            std::this_thread::yield();
+        const int64_t w = s->work.load(std::memory_order_acquire);
+        const int nl = s->launches_inflight.load(std::memory_order_relaxed);
+        if (w > nl) {
+            reap_unlocked(s);
+            {
+                std::lock_guard<std::mutex> g(s->mu);
+                progress_locked(s);
+            }
+            last_active = now_us();
             continue;
         }
-        {
-            std::unique_lock<std::mutex> q(s->qmu);
-            s->wake.wait_for(q, std::chrono::milliseconds(1),
-                             [s] { return !s->queue.empty() || !s->run_thread.load(std::memory_order_acquire); });
+        const double t = now_us();
+        if (nl > 0) {
+            if (t - s->last_reap.load(std::memory_order_relaxed) >= THREAD_REAP_US && reap_unlocked(s)) {
+                std::lock_guard<std::mutex> g(s->mu);
+                progress_locked(s);
+            }
+            last_active = t;
+            continue;
         }
+        if (t - last_active < SPIN_US) continue;
+        std::unique_lock<std::mutex> q(s->qmu);
+        s->wake.wait_for(q, std::chrono::milliseconds(1), [s] {
+            return s->work.load(std::memory_order_acquire) > 0 || !s->run_thread.load(std::memory_order_acquire);
+        });
     }
 }
 
@@ -406,21 +563,20 @@ int submit(mdt_server s, Item *it, mdt_request *req)
     r->server_item = it;
     it->t_submit = now_us();
     {
-        std::lock_guard<std::mutex> g(s->mu);
+        std::lock_guard<std::mutex> q(s->qmu);
         s->submitted++;
         if (s->first_submit < 0) s->first_submit = it->t_submit;
-    }
-    {
-        std::lock_guard<std::mutex> q(s->qmu);
         s->queue.push_back(it);
+        s->work.fetch_add(1, std::memory_order_release);  // under qmu: a sleeping thread sees it
     }
+    // Light load (fewer launches in flight than streams, or no progress
+    // thread): the submitter runs a progress round itself, so its request is
+    // admitted and launched now.  Under load it only queues: the progress
+    // thread cuts whatever has queued into batched launches, which keeps the
+    // cost per submit low and the launches few.
+    const bool thread = s->run_thread.load(std::memory_order_acquire);
+    if (!thread || s->launches_inflight.load(std::memory_order_relaxed) < (int)s->streams.size()) progress(s);
     s->wake.notify_one();
-    // light load: dispatch right away when no progress round is running and
-    // nothing else waits; under load the progress thread batches instead
-    if (s->light.load(std::memory_order_relaxed) && s->mu.try_lock()) {
-        progress_locked(s);
-        s->mu.unlock();
-    }
     *req = r;
     return MDT_SUCCESS;
 }
@@ -461,8 +617,10 @@ MDT_API int mdt_server_create(const mdt_server_config *cfg, mdt_server *out)
         delete s;
         return MDT_ERR_NO_MEM;
     }
-    s->arena.size = c.arena_bytes;
-    s->arena.free_[0] = c.arena_bytes;
+    s->arena.init(s->arena.base, c.arena_bytes);
+    s->lat_us.reserve(1 << 20);
+    s->queue_us.reserve(1 << 20);
+    s->run_us.reserve(1 << 20);
     s->streams.resize(c.nstreams);
     int rc = MDT_SUCCESS;
     for (auto &st : s->streams) {
@@ -498,6 +656,11 @@ MDT_API int mdt_server_free(mdt_server *ps)
         std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
     (void)hipDeviceSynchronize();
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        std::lock_guard<std::mutex> q(s->qmu);
+        take_back_released(s);
+    }
     for (auto &st : s->streams) {
         for (auto &sl : st.slots) {
             if (sl.batch) mdt_batch_free(&sl.batch);
@@ -570,7 +733,17 @@ MDT_API int mdt_server_request_test(mdt_server srv, mdt_request req, int *flag)
 {
     Item *it = item_of(req);
     if (!valid_server(srv) || !it || !flag) return MDT_ERR_ARG;
-    if (it->state.load(std::memory_order_acquire) != 3 && !srv->run_thread.load()) progress(srv);
+    if (it->state.load(std::memory_order_acquire) != 3) {
+        if (!srv->run_thread.load()) {
+            progress(srv);
+        } else if (now_us() - srv->last_reap.load(std::memory_order_relaxed) >= TEST_REAP_US && srv->mu.try_lock()) {
+            // the caller reaps (as a caller polling its own event would); the
+            // progress thread keeps to launching
+            reap_locked(srv);
+            progress_locked(srv);
+            srv->mu.unlock();
+        }
+    }
     *flag = it->state.load(std::memory_order_acquire) == 3;
     return MDT_SUCCESS;
 }
@@ -579,9 +752,11 @@ MDT_API int mdt_server_request_wait(mdt_server srv, mdt_request req)
 {
     Item *it = item_of(req);
     if (!valid_server(srv) || !it) return MDT_ERR_ARG;
-    while (it->state.load(std::memory_order_acquire) != 3) {
-        if (!srv->run_thread.load()) progress(srv);
-        else std::this_thread::sleep_for(std::chrono::microseconds(10));
+    int flag = 0;
+    for (;;) {
+        mdt_server_request_test(srv, req, &flag);
+        if (flag) break;
+        std::this_thread::yield();
     }
     return MDT_SUCCESS;
 }
@@ -606,13 +781,12 @@ MDT_API int mdt_server_request_release(mdt_server srv, mdt_request *preq)
     if (!valid_server(srv) || !it) return MDT_ERR_ARG;
     if (it->state.load(std::memory_order_acquire) != 3) return MDT_ERR_STATE;
     {
-        std::lock_guard<std::mutex> g(srv->mu);
-        if (it->arena_off >= 0) srv->arena.release(it->arena_off, std::max<int64_t>(it->nbytes, 1));
-        // admitted requests hold their charge until released
-        if (it->arena_off >= 0 || it->unpack) srv->inflight -= it->charge;
+        // the next progress round returns its arena range and budget charge
+        // (the client never waits for a round in progress)
+        std::lock_guard<std::mutex> q(srv->qmu);
+        srv->released.push_back(it);
+        srv->work.fetch_add(1, std::memory_order_release);
     }
-    release(it->type);
-    delete it;
     (*preq)->magic = 0;
     delete *preq;
     *preq = nullptr;
@@ -651,6 +825,8 @@ MDT_API int mdt_server_stats_get(mdt_server srv, mdt_server_stats *out)
 {
     if (!valid_server(srv) || !out) return MDT_ERR_ARG;
     std::lock_guard<std::mutex> g(srv->mu);
+    std::lock_guard<std::mutex> q(srv->qmu);
+    take_back_released(srv);
     out->submitted = srv->submitted;
     out->completed = srv->completed;
     out->failed = srv->failed;

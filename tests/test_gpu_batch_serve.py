@@ -113,11 +113,11 @@ def test_batch_equals_alone(env):
     b = mdt.Batch()
     for (t, src, n), o in zip(plan, offs):
         assert b.add_pack(src.data_ptr(), 1, t, 0, out.data_ptr() + int(o) + 3, n) == n
-    for policy in (0, 1):
+    for policy, wgs in ((0, 4), (1, 4), (0, 0)):
         for graph in (1, 0):
             for tc in (256, 4096):
-                note(f"batch policy={policy} graph={graph} tile={tc}")
-                b.set_config(mdt.BatchConfig(tc, 4, policy, graph))
+                note(f"batch policy={policy} wgs={wgs} graph={graph} tile={tc}")
+                b.set_config(mdt.BatchConfig(tc, wgs, policy, graph))
                 for rep in range(3):
                     out.fill_(0)
                     b.launch(ms)
@@ -125,7 +125,7 @@ def test_batch_equals_alone(env):
                     _ = (out[:1024].sum().item())  # eager work between replays
                     assert first_diff(to_host(out), ref) is None, (policy, graph, tc, rep)
     cfg = b.autotune(ms)
-    assert cfg.tile_chunks in (256, 512, 1024, 2048, 4096) and 1 <= cfg.wgs_per_cu <= 16
+    assert cfg.tile_chunks in (256, 512, 1024, 2048, 4096) and 0 <= cfg.wgs_per_cu <= 16
     out.fill_(0)
     b.launch(ms)
     assert first_diff(to_host(out), ref) is None
@@ -151,6 +151,48 @@ def test_batch_equals_alone(env):
         torch.cuda.synchronize()
     for k in back:
         assert first_diff(to_host(back[k]), exp_back[k]) is None, k
+
+
+def test_batch_mixed_directions(env):
+    # pack and unpack requests added in interleaved order run as two launches
+    # (pack first); every request gives the oracle's bytes
+    torch, mdt = env
+    specs = [inputs.particle_struct(), inputs.halo_face(64, 2, 1, "hi"), ("vector", 3000, 3, 7, inputs.DOUBLE)]
+    types = [mdt.build_type(sp) for sp in specs]
+    orc = [obuild(sp) for sp in specs]
+    counts = [5000, 1, 1]
+    srcs, outs, exps, pks, dsts, dexp = [], [], [], [], [], []
+    for i, (sp, o, c) in enumerate(zip(specs, orc, counts)):
+        a = o.attrs()
+        nb = (c - 1) * a["extent"] + a["true_ub"] + 8
+        h = inputs.random_bytes(nb, seed=50 + i)
+        srcs.append(to_dev(h))
+        full = o.pack(h, 0, c)
+        exps.append(full)
+        outs.append(zeros_dev(full.size, 0))
+        pks.append(to_dev(full))
+        canary = np.full(nb, 0x33, np.uint8)
+        e = canary.copy()
+        o.unpack(full, e, 0, c)
+        dexp.append(e)
+        dsts.append(to_dev(canary))
+    ms = mdt.Stream(torch.cuda.current_stream().cuda_stream)
+    for wgs in (0, 2):
+        note(f"mixed-direction batch wgs={wgs}")
+        for d, o in zip(dsts, orc):
+            d.fill_(0x33)
+        for x in outs:
+            x.fill_(0)
+        b = mdt.Batch()
+        for i, (t, c) in enumerate(zip(types, counts)):
+            b.add_unpack(pks[i].data_ptr(), exps[i].size, dsts[i].data_ptr(), c, t, 0)
+            b.add_pack(srcs[i].data_ptr(), c, t, 0, outs[i].data_ptr(), -1)
+        b.set_config(mdt.BatchConfig(1024, wgs, 0, 1))
+        b.launch(ms)
+        torch.cuda.synchronize()
+        for i in range(len(specs)):
+            assert first_diff(to_host(outs[i]), exps[i]) is None, (wgs, i)
+            assert first_diff(to_host(dsts[i]), dexp[i]) is None, (wgs, i)
 
 
 def test_server_mix_equals_alone(env):
