@@ -170,6 +170,34 @@ MDT_API int mdt_type_commit(mdt_type *t);
  * device to be idle. */
 MDT_API int mdt_type_free(mdt_type *t);
 
+/* Layout program summary of a committed type (not part of the paper's
+ * interface: it reports which of this library's kernels a full transfer of
+ * the type takes, for tests and tuning).
+ *   kind:          0 empty, 1 contiguous, 2 one shape (loops over a run
+ *                  list), 3 group table (irregular)
+ *   groups, runs:  groups of the table (1 for kinds 1-2), runs of one element
+ *   records:       1 when the stream is read as equally spaced records of
+ *                  short runs (LDS-staged record kernels), else 0
+ *   record_bytes, record_stride: packed bytes and byte stride of a record
+ *   pack_table:    0 none, 1 per-byte table, 2 per-chunk table (records)
+ *   unpack_table:  0 none (unpack takes the chunk path), 1 per-byte table,
+ *                  2 per-dword table (records)
+ *   device_bytes:  size of the type's resident device tables
+ * Errors: MDT_ERR_TYPE for an invalid or uncommitted handle, MDT_ERR_ARG
+ * for a NULL out. */
+typedef struct mdt_layout_info {
+    int32_t kind;
+    int32_t records;
+    int64_t groups;
+    int64_t runs;
+    int64_t record_bytes;
+    int64_t record_stride;
+    int32_t pack_table;
+    int32_t unpack_table;
+    int64_t device_bytes;
+} mdt_layout_info;
+MDT_API int mdt_type_layout_info(mdt_type t, mdt_layout_info *out);
+
 /* Attributes (valid on uncommitted types). */
 MDT_API int mdt_type_size(mdt_type t, mdt_count *size);
 MDT_API int mdt_type_get_extent(mdt_type t, mdt_aint *lb, mdt_aint *extent);

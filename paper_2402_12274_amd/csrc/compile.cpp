@@ -756,6 +756,10 @@ void lower_records(const Layout &L, Compiled &C)
         return;
     }
     if (X <= 0 || X > REC_MAX_X || U < 1 || U > REC_MAX_U || X > 4 * U) return;
+    // records of long runs move at full speed on the chunk path (one run per
+    // 16-byte chunk, whole tiles inside one run); staging them in LDS only
+    // shrinks the grid
+    if (U >= REC_MIN_RUN * (int64_t)S.leaf.size()) return;
     int64_t lo = INT64_MAX, hi = INT64_MIN;
     for (const Run &r : S.leaf) {
         lo = std::min(lo, r.off);

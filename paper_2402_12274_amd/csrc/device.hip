@@ -245,7 +245,14 @@ static int64_t launch_grid(int64_t ntiles)
 
 int64_t default_tile_chunks(int64_t nchunks)
 {
-    // 4 chunks per lane for large transfers, 1 for small ones
+    // 4 chunks per lane for large transfers, 1 for small ones (MDT_CHUNK_TILE
+    // = 64..1024 fixes it, for tuning)
+    static const int64_t fixed = [] {
+        const char *e = getenv("MDT_CHUNK_TILE");
+        int v = e && *e ? atoi(e) : 0;
+        return (int64_t)(v == 64 || v == 128 || v == 256 || v == 512 || v == 1024 ? v : 0);
+    }();
+    if (fixed) return fixed;
     return nchunks >= ((int64_t)1 << 19) ? 1024 : 256;
 }
 

@@ -149,6 +149,7 @@ struct DevShape {
 // tile's typed span in LDS and mapping bytes through per-record tables.
 constexpr int32_t REC_MAX_U = 4096;
 constexpr int32_t REC_MAX_X = 4096;
+constexpr int32_t REC_MIN_RUN = 64;  // the view is used when runs average fewer bytes
 
 struct DevRecords {
     int32_t on;        // 1 when the view applies

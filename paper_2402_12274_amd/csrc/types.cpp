@@ -458,6 +458,34 @@ MDT_API int mdt_type_free(mdt_type *t)
     return MDT_SUCCESS;
 }
 
+MDT_API int mdt_type_layout_info(mdt_type t, mdt_layout_info *out)
+{
+    CHECK_TYPE(t);
+    if (!out) return MDT_ERR_ARG;
+    TypeNode *n = as_node(t);
+    if (!n->committed.load() || !n->comp) return MDT_ERR_TYPE;
+    const Compiled &C = *n->comp;
+    const DevLayout &L = C.host;
+    std::memset(out, 0, sizeof *out);
+    out->kind = L.kind;
+    out->groups = L.kind == KIND_MULTI ? L.G : (L.kind == KIND_EMPTY ? 0 : 1);
+    out->runs = L.nruns;
+    out->records = L.rec.on;
+    if (L.rec.on) {
+        out->record_bytes = L.rec.U;
+        out->record_stride = L.rec.X;
+        out->pack_table = L.rec.ctab ? 2 : 1;
+        out->unpack_table = L.rec.dtab ? 2 : (L.rec.ttab ? 1 : 0);
+    }
+    int64_t b = (int64_t)(C.shapes.size() * sizeof(DevShape) + sizeof(DevLayout));
+    for (auto &v : C.leaf_store) b += (int64_t)(v.size() * sizeof(int64_t));
+    b += (int64_t)((C.gdisp.size() + C.gpre.size() + C.grpre.size()) * sizeof(int64_t));
+    b += (int64_t)((C.gshape.size() + C.gdir.size()) * sizeof(int32_t));
+    b += (int64_t)((C.rec_ptab.size() + C.rec_ttab.size() + C.rec_ctab.size() + C.rec_dtab.size()) * sizeof(uint32_t));
+    out->device_bytes = b;
+    return MDT_SUCCESS;
+}
+
 MDT_API int mdt_type_size(mdt_type t, mdt_count *size)
 {
     CHECK_TYPE(t);

@@ -155,15 +155,34 @@ __device__ __forceinline__ void pack_chunk(const DevLayout &L, const XferArgs &A
     if (n == 16 && l.rem >= 16) {
         acc = load16(src + l.addr);
     } else {
-        for (;;) {
-            int take = l.rem < n ? (int)l.rem : n;
-            if (take <= 0) break;  // unreachable for a well-formed layout; never spin
-            gather_part(acc, k, src + l.addr, take);
-            p += take;
-            k += take;
-            n -= take;
-            if (n <= 0) break;
+        // the first two runs are located before either is read, so their
+        // loads are in flight together (chunks of small blocks mostly hold
+        // two runs); further runs follow one at a time
+        int take = l.rem < n ? (int)l.rem : n;
+        int take2 = 0;
+        Loc l2 = l;
+        if (take > 0 && take < n) {
+            l2 = locate<KIND>(L, p + (uint64_t)take, A.elem1);
+            take2 = l2.rem < n - take ? (int)l2.rem : n - take;
+            if (take2 < 0) take2 = 0;
+        }
+        if (take > 0) gather_part(acc, k, src + l.addr, take);
+        if (take2 > 0) gather_part(acc, k + take, src + l2.addr, take2);
+        if (take > 0 && take2 > 0 && take + take2 < n) {
+            p += (uint64_t)(take + take2);
+            k += take + take2;
+            n -= take + take2;
             l = locate<KIND>(L, p, A.elem1);
+            for (;;) {
+                int t = l.rem < n ? (int)l.rem : n;
+                if (t <= 0) break;  // unreachable for a well-formed layout; never spin
+                gather_part(acc, k, src + l.addr, t);
+                p += t;
+                k += t;
+                n -= t;
+                if (n <= 0) break;
+                l = locate<KIND>(L, p, A.elem1);
+            }
         }
     }
     uint8_t *dst = A.packed - A.head + 16 * c;

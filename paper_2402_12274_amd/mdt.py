@@ -55,6 +55,12 @@ class BatchConfig(C.Structure):
     _fields_ = [("tile_chunks", C.c_int), ("wgs_per_cu", C.c_int), ("policy", C.c_int), ("use_graph", C.c_int)]
 
 
+class LayoutInfo(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("records", C.c_int32), ("groups", C.c_int64), ("runs", C.c_int64),
+                ("record_bytes", C.c_int64), ("record_stride", C.c_int64), ("pack_table", C.c_int32),
+                ("unpack_table", C.c_int32), ("device_bytes", C.c_int64)]
+
+
 class ServerConfig(C.Structure):
     _fields_ = [("nstreams", C.c_int), ("budget_bytes", C.c_int64), ("max_batch", C.c_int),
                 ("max_inflight", C.c_int), ("arena_bytes", C.c_int64)]
@@ -85,6 +91,7 @@ _SIGS = {
     "mdt_type_commit": ([C.POINTER(_P)], _INT),
     "mdt_type_free": ([C.POINTER(_P)], _INT),
     "mdt_type_size": ([_P, _I64P], _INT),
+    "mdt_type_layout_info": ([_P, C.POINTER(LayoutInfo)], _INT),
     "mdt_type_get_extent": ([_P, _I64P, _I64P], _INT),
     "mdt_type_get_true_extent": ([_P, _I64P, _I64P], _INT),
     "mdt_type_iov_len": ([_P, _I64, _I64P, _I64P], _INT),
@@ -191,6 +198,13 @@ class Type:
         v = C.c_int64()
         check(_lib.mdt_type_size(self.h, C.byref(v)), "size")
         return v.value
+
+    def layout_info(self) -> dict:
+        """Summary of the committed layout program (kind, groups, runs, record
+        view and its tables, resident device bytes)."""
+        v = LayoutInfo()
+        check(_lib.mdt_type_layout_info(self.h, C.byref(v)), "layout_info")
+        return {f: getattr(v, f) for f, _ in v._fields_}
 
     def extent(self):
         a, b = C.c_int64(), C.c_int64()

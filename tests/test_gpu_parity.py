@@ -176,24 +176,29 @@ def test_long_runs_partial(mdt):
 
 C, I16, I32, U8 = ("basic", "CHAR"), ("basic", "INT16"), ("basic", "INT32"), ("basic", "UINT8")
 RECORD_CASES = [
-    # (spec, count, origin, chunk): record views with odd strides, gaps at
-    # both ends of a record, map order unlike address order, and records
-    # large enough for the byte-table paths (U > 256 or X > 1024)
-    (("resized", 0, 9, ("struct", [1, 1, 1], [0, 2, 7], [C, I16, C])), 30001, 3, 4099),
-    (("hvector", 20000, 3, 4, U8), 1, 1, 5003),
-    (("hvector", 5000, 1, 12, I32), 1, 2, 1 << 12),
-    (("struct", [1, 1, 3], [16, 0, 8], [inputs.DOUBLE, I32, C]), 40000, 5, 65537),
-    (("resized", 0, 320, ("contiguous", 75, I32)), 3000, 0, (1 << 15) + 1),
-    (("resized", 0, 1100, ("struct", [1, 1], [0, 600], [("contiguous", 50, inputs.DOUBLE),
-                                                        ("contiguous", 100, I32)])), 500, 7, 30011),
-    (("resized", 0, 8, ("struct", [1, 1], [0, 12], [I32, I32])), 20000, 1, 9999),
+    # (spec, count, origin, chunk, (records, pack_table, unpack_table)):
+    # record views with odd strides, gaps at both ends of a record, map order
+    # unlike address order, records of many small runs large enough for the
+    # byte-table paths (U > 256, X > 1024), interleaved records (unpack on the
+    # chunk path), and records of one long run (left to the chunk path)
+    (("resized", 0, 9, ("struct", [1, 1, 1], [0, 2, 7], [C, I16, C])), 30001, 3, 4099, (1, 2, 2)),
+    (("hvector", 20000, 3, 4, U8), 1, 1, 5003, (1, 2, 2)),
+    (("hvector", 5000, 1, 12, I32), 1, 2, 1 << 12, (1, 2, 2)),
+    (("struct", [1, 1, 3], [16, 0, 8], [inputs.DOUBLE, I32, C]), 40000, 5, 65537, (1, 2, 2)),
+    (("resized", 0, 600, ("hindexed", [8] * 40, [14 * i + i % 3 for i in range(40)], C)), 3000, 0, (1 << 15) + 1,
+     (1, 1, 2)),
+    (("resized", 0, 1200, ("hindexed", [5] * 60, [19 * i + i % 2 for i in range(60)], C)), 500, 7, 30011, (1, 1, 1)),
+    (("resized", 0, 320, ("contiguous", 75, I32)), 3000, 0, (1 << 15) + 1, (0, 0, 0)),
+    (("resized", 0, 8, ("struct", [1, 1], [0, 12], [I32, I32])), 20000, 1, 9999, (1, 2, 0)),
 ]
 
 
 @pytest.mark.parametrize("i", range(len(RECORD_CASES)))
 def test_record_layouts(mdt, i):
-    spec, count, origin, chunk = RECORD_CASES[i]
+    spec, count, origin, chunk, path = RECORD_CASES[i]
     note(f"record layout {i}: {str(spec)[:70]} count={count}")
+    info = mdt.build_type(spec).layout_info()
+    assert (info["records"], info["pack_table"], info["unpack_table"]) == path, info
     o = obuild(spec)
     a = o.attrs()
     nbytes = origin + (count - 1) * a["extent"] + a["true_ub"] + 16

@@ -136,3 +136,29 @@ def test_regular_layout_description_is_constant_size():
     b, ln = t.iov(n * n - 1, 1)
     assert b[0] == ((n - 1) * n * n + (n - 1) * n) * 8 and ln[0] == 8
     assert ctypes.sizeof(mdt.Iov) == 16
+
+
+def test_layout_info_reports_the_program():
+    # the compiled program's shape, and which record tables the kernels use
+    c = mdt.build_type(("contiguous", 1 << 20, inputs.DOUBLE)).layout_info()
+    assert c["kind"] == 1 and c["runs"] == 1 and c["records"] == 0
+    # a face of a 512^3 array: one shape over 510^2 runs, device tables of
+    # constant size whatever the segment count
+    f = mdt.build_type(inputs.halo_face(512, 1, 2, "lo")).layout_info()
+    assert f["kind"] == 2 and f["runs"] == 510 * 510 and f["records"] == 0 and f["device_bytes"] < 4096
+    # particle records: 33 packed bytes every 40, chunk and dword tables
+    p = mdt.build_type(inputs.particle_struct()).layout_info()
+    assert (p["records"], p["record_bytes"], p["record_stride"], p["pack_table"], p["unpack_table"]) == \
+        (1, 33, 40, 2, 2)
+    # irregular blocks: a group table, O(blocks) device bytes
+    lens, disps = inputs.hindexed_blocks(nblocks=5000, span=1 << 20, seed=2)
+    h = mdt.build_type(inputs.hindexed_type(lens, disps)).layout_info()
+    assert h["kind"] == 3 and h["groups"] >= 4000 and h["device_bytes"] >= 5000 * 16
+    # an uncommitted handle has no program
+    import ctypes
+
+    raw = ctypes.c_void_p()
+    assert mdt._lib.mdt_type_contiguous(3, mdt.basic("DOUBLE").h, ctypes.byref(raw)) == 0
+    info = mdt.LayoutInfo()
+    assert mdt._lib.mdt_type_layout_info(raw, ctypes.byref(info)) == mdt.ERR_TYPE
+    assert mdt._lib.mdt_type_free(ctypes.byref(raw)) == 0
