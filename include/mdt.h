@@ -283,12 +283,17 @@ MDT_API int mdt_batch_add_unpack(mdt_batch b, const void *inbuf, mdt_count insiz
                                  mdt_count outcount, mdt_type t, mdt_count outoffset,
                                  mdt_count *actual_unpack_bytes);
 /* Tuning knobs of the persistent launch.  policy: 0 = static strided split
- * of tiles over workgroups, 1 = dynamic (atomic tile counter). */
+ * of tiles over workgroups, 1 = dynamic (atomic tile counter).  order: 1 =
+ * tiles run in the order of the typed address they start at, so requests
+ * that touch the same memory (faces sharing cache lines) run together; with
+ * the static policy each XCD (its own L2) takes one contiguous slice of
+ * that order. */
 typedef struct mdt_batch_config {
     int tile_chunks;    /* 16-byte chunks per workgroup tile: 256, 512, 1024, 2048, 4096 */
     int wgs_per_cu;     /* persistent workgroups per compute unit, 1..16; 0: one workgroup per tile */
     int policy;         /* 0 static, 1 dynamic */
     int use_graph;      /* 1 = capture and replay a HIP graph, 0 = direct launches */
+    int order;          /* 0 request order, 1 typed-address order */
 } mdt_batch_config;
 MDT_API int mdt_batch_set_config(mdt_batch b, const mdt_batch_config *cfg);
 MDT_API int mdt_batch_get_config(mdt_batch b, mdt_batch_config *cfg);

@@ -43,7 +43,8 @@ struct BatchHeader {
     int64_t nreq_dir[2];    // requests per direction
     int64_t ntiles_dir[2];  // tiles per direction
     int64_t tile_chunks;
-    int64_t pad[3];
+    int64_t ordered;        // 1: slots map to tiles through the order table
+    int64_t nslots_dir[2];  // order-table slots per direction (>= tiles; -1 entries are empty)
 };
 
 // Chunks [c0, cend) of one request, with the single-request bodies.
@@ -103,14 +104,18 @@ template <int POLICY, int UNPACK>
 __global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restrict__ H,
                                                     const ReqDesc *__restrict__ R,
                                                     const int64_t *__restrict__ tile0,
+                                                    const int32_t *__restrict__ order,
                                                     unsigned long long *counter)
 {
     extern __shared__ __align__(16) uint8_t lds_dyn[];
     __shared__ int64_t s_t;
     const int64_t T = H->tile_chunks;
-    // this direction's requests [r0, r1) and tiles [t_begin, t_end)
+    const bool ordered = H->ordered != 0;
+    // this direction's requests [r0, r1) and index range [t_begin, t_end):
+    // tiles, or slots of the order table
     const int64_t r0 = UNPACK ? H->nreq_dir[0] : 0, r1 = r0 + H->nreq_dir[UNPACK];
-    const int64_t t_begin = UNPACK ? H->ntiles_dir[0] : 0, t_end = t_begin + H->ntiles_dir[UNPACK];
+    const int64_t t_begin = ordered ? (UNPACK ? H->nslots_dir[0] : 0) : (UNPACK ? H->ntiles_dir[0] : 0);
+    const int64_t t_end = t_begin + (ordered ? H->nslots_dir[UNPACK] : H->ntiles_dir[UNPACK]);
     int64_t t;
     if (POLICY == 0) {
         t = t_begin + blockIdx.x;
@@ -120,26 +125,29 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restric
         t = uniform64(s_t);
     }
     while (t < t_end) {
-        // request holding tile t: last r with tile0[r] <= t
-        int64_t lo = r0, hi = r1 - 1;
-        while (lo < hi) {
-            int64_t mid = (lo + hi + 1) >> 1;
-            if (tile0[mid] <= t) lo = mid; else hi = mid - 1;
+        const int64_t tile = ordered ? (int64_t)order[t] : t;  // -1: an empty slot
+        if (tile >= 0) {
+            // request holding the tile: last r with tile0[r] <= tile
+            int64_t lo = r0, hi = r1 - 1;
+            while (lo < hi) {
+                int64_t mid = (lo + hi + 1) >> 1;
+                if (tile0[mid] <= tile) lo = mid; else hi = mid - 1;
+            }
+            const ReqDesc &D = R[lo];
+            const DevLayout &L = const_layout(D.lay);
+            XferArgs A;
+            A.typed = D.typed;
+            A.packed = D.packed;
+            A.off = D.off;
+            A.nbytes = D.nbytes;
+            A.head = D.head;
+            A.nchunks = D.nchunks;
+            A.tile_chunks = T;
+            A.elem1 = D.elem1;
+            int64_t c0 = (tile - tile0[lo]) * T;
+            int64_t cend = c0 + T < D.nchunks ? c0 + T : D.nchunks;
+            run_tile(L, A, UNPACK, D.dense, D.kind, c0, cend, lds_dyn);
         }
-        const ReqDesc &D = R[lo];
-        const DevLayout &L = const_layout(D.lay);
-        XferArgs A;
-        A.typed = D.typed;
-        A.packed = D.packed;
-        A.off = D.off;
-        A.nbytes = D.nbytes;
-        A.head = D.head;
-        A.nchunks = D.nchunks;
-        A.tile_chunks = T;
-        A.elem1 = D.elem1;
-        int64_t c0 = (t - tile0[lo]) * T;
-        int64_t cend = c0 + T < D.nchunks ? c0 + T : D.nchunks;
-        run_tile(L, A, UNPACK, D.dense, D.kind, c0, cend, lds_dyn);
         if (POLICY == 0) {
             t += gridDim.x;
         } else {
@@ -166,7 +174,7 @@ struct BatchReq {
 struct mdt_batch_s {
     uint32_t magic = BATCH_MAGIC;
     std::vector<BatchReq> reqs;
-    mdt_batch_config cfg{1024, 4, 0, 1};
+    mdt_batch_config cfg{1024, 4, 0, 1, 0};
     bool dirty = true;
     int device = -1;
     int ncu = 0;
@@ -177,14 +185,21 @@ struct mdt_batch_s {
     hipEvent_t staged = nullptr; // the last upload from h_stage has been consumed
     unsigned long long *d_counter = nullptr;  // [2] tile counters, one per direction
     int64_t ntiles_dir[2] = {0, 0};
+    int64_t nslots_dir[2] = {0, 0};  // order-table slots per direction (ordered schedule)
+    // tile order table (ordered schedule): device copy and pinned staging
+    int32_t *d_order = nullptr;
+    int32_t *h_order = nullptr;
+    size_t order_cap = 0;
+    bool staged_order = false;  // the uploaded table matches the current schedule
     int32_t lds = 0;  // dynamic LDS of the persistent kernel (largest dense request)
     int32_t dirs = 0; // bit 0: has pack requests, bit 1: has unpack requests
     // captured launch
     hipGraphExec_t exec = nullptr;
     hipStream_t cap_stream = nullptr;
     int graph_grid[2] = {-1, -1};
-    int graph_policy = -1, graph_lds = -1;
+    int graph_policy = -1, graph_lds = -1, graph_ordered = -1;
     uint8_t *graph_buf = nullptr;
+    int32_t *graph_order = nullptr;
 };
 
 namespace {
@@ -247,6 +262,85 @@ int init_device(mdt_batch_s *b)
     return MDT_SUCCESS;
 }
 
+// XCDs of the device: workgroup b of a launch runs on XCD b mod XCDS
+// (round-robin dispatch), and each XCD has its own L2.
+constexpr int XCDS = 8;
+
+// Typed-address order of each direction's tiles (the address a tile's first
+// packed byte comes from or goes to).  With the static policy slot t of a
+// direction runs on XCD t mod XCDS, so the sorted tiles are dealt out as
+// XCDS contiguous slices, one per XCD, each run in address order.
+int build_order(mdt_batch_s *b, const ReqDesc *D, const int64_t *tile0, const BatchHeader &H)
+{
+    const int64_t T = b->cfg.tile_chunks;
+    const int64_t total = H.ntiles_dir[0] + H.ntiles_dir[1];
+    if (total > INT32_MAX / 2) return MDT_ERR_COUNT;
+    // slots: tiles rounded up to a multiple of XCDS per direction
+    const size_t need = (size_t)(total + 2 * XCDS);
+    if (need > b->order_cap) {
+        size_t cap = std::max<size_t>(need, 2 * b->order_cap);
+        (void)hipDeviceSynchronize();  // a launch in flight may read the old table
+        release_graph(b);
+        if (b->d_order) (void)hipFree(b->d_order);
+        if (b->h_order) (void)hipHostFree(b->h_order);
+        b->d_order = nullptr;
+        b->h_order = nullptr;
+        b->order_cap = 0;
+        hipError_t e = hipMalloc((void **)&b->d_order, cap * sizeof(int32_t));
+        if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_order, cap * sizeof(int32_t), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            set_hip_error((int)e);
+            return MDT_ERR_NO_MEM;
+        }
+        b->order_cap = cap;
+    }
+    // requests in descriptor order are those of reqs filtered by direction
+    std::vector<const BatchReq *> byk;
+    for (int dir = 0; dir < 2; dir++)
+        for (auto &r : b->reqs)
+            if (r.d.unpack == dir) byk.push_back(&r);
+    std::vector<std::pair<uint64_t, int32_t>> keys;
+    int64_t slot0 = 0, k0 = 0;
+    for (int dir = 0; dir < 2; dir++) {
+        keys.clear();
+        const int64_t nreq = H.nreq_dir[dir];
+        for (int64_t k = k0; k < k0 + nreq; k++) {
+            const ReqDesc &d = D[k];
+            const DevLayout &L = byk[(size_t)k]->type->comp->host;
+            for (int64_t t = tile0[k]; t < tile0[k + 1]; t++) {
+                int64_t p = (t - tile0[k]) * T * 16 - d.head;
+                if (p < 0) p = 0;
+                const uint64_t sp = (uint64_t)(d.off + p);
+                Loc l;
+                if (L.kind == KIND_CONTIG) l = locate<KIND_CONTIG>(L, sp, d.elem1);
+                else if (L.kind == KIND_SINGLE) l = locate<KIND_SINGLE>(L, sp, d.elem1);
+                else l = locate<KIND_MULTI>(L, sp, d.elem1);
+                keys.emplace_back((uint64_t)((uintptr_t)d.typed + (uint64_t)l.addr), (int32_t)t);
+            }
+        }
+        k0 += nreq;
+        std::stable_sort(keys.begin(), keys.end(),
+                         [](const std::pair<uint64_t, int32_t> &x, const std::pair<uint64_t, int32_t> &y) {
+                             return x.first < y.first;
+                         });
+        const int64_t n = (int64_t)keys.size();
+        int64_t nslots = n;
+        if (b->cfg.policy == 0 && n > 0) {
+            const int64_t C = (n + XCDS - 1) / XCDS;
+            nslots = C * XCDS;
+            for (int64_t t = 0; t < nslots; t++) {
+                const int64_t p = (t % XCDS) * C + t / XCDS;
+                b->h_order[slot0 + t] = p < n ? keys[(size_t)p].second : -1;
+            }
+        } else {
+            for (int64_t t = 0; t < n; t++) b->h_order[slot0 + t] = keys[(size_t)t].second;
+        }
+        b->nslots_dir[dir] = nslots;
+        slot0 += nslots;
+    }
+    return MDT_SUCCESS;
+}
+
 // Upload descriptors and the tile prefix (stream-ordered) if the batch changed.
 int stage(mdt_batch_s *b, hipStream_t s)
 {
@@ -285,9 +379,20 @@ int stage(mdt_batch_s *b, hipStream_t s)
         if (acc > acc0) b->dirs |= 1 << dir;
     }
     tile0[k] = acc;
+    b->nslots_dir[0] = b->nslots_dir[1] = 0;
+    if (b->cfg.order) {
+        rc = build_order(b, D, tile0, H);
+        if (rc) return rc;
+    }
+    H.ordered = b->cfg.order ? 1 : 0;
+    H.nslots_dir[0] = b->nslots_dir[0];
+    H.nslots_dir[1] = b->nslots_dir[1];
     std::memcpy(b->h_stage, &H, sizeof H);
     size_t n = tile_off(b->cap) + (b->reqs.size() + 1) * sizeof(int64_t);
     e = hipMemcpyAsync(b->d_buf, b->h_stage, n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && b->cfg.order && b->nslots_dir[0] + b->nslots_dir[1] > 0)
+        e = hipMemcpyAsync(b->d_order, b->h_order, (size_t)(b->nslots_dir[0] + b->nslots_dir[1]) * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipEventRecord(b->staged, s);
     if (e != hipSuccess) {
         set_hip_error((int)e);
@@ -301,7 +406,7 @@ int stage(mdt_batch_s *b, hipStream_t s)
 // (persistent), or one per tile when wgs_per_cu is 0.
 int grid_of(const mdt_batch_s *b, int dir)
 {
-    const int64_t n = b->ntiles_dir[dir];
+    const int64_t n = b->cfg.order ? b->nslots_dir[dir] : b->ntiles_dir[dir];
     int64_t g = b->cfg.wgs_per_cu > 0 ? std::min<int64_t>((int64_t)b->ncu * b->cfg.wgs_per_cu, n) : n;
     return (int)std::min<int64_t>(std::max<int64_t>(1, g), INT32_MAX);
 }
@@ -311,6 +416,7 @@ void enqueue_kernels(mdt_batch_s *b, hipStream_t s)
     const BatchHeader *H = (const BatchHeader *)b->d_buf;
     const ReqDesc *R = (const ReqDesc *)(b->d_buf + desc_off());
     const int64_t *tile0 = (const int64_t *)(b->d_buf + tile_off(b->cap));
+    const int32_t *ord = b->d_order;
     // one kernel per direction: a mixed batch runs its pack tiles and its
     // unpack tiles as two launches (each kernel skips the other direction)
     for (int dir = 0; dir < 2; dir++) {
@@ -319,11 +425,11 @@ void enqueue_kernels(mdt_batch_s *b, hipStream_t s)
         unsigned long long *ctr = b->d_counter + dir;
         if (b->cfg.policy == 1) {
             hipLaunchKernelGGL(batch_counter_reset, dim3(1), dim3(1), 0, s, ctr);
-            if (dir) hipLaunchKernelGGL((batch_kernel<1, 1>), grid, dim3(256), (size_t)b->lds, s, H, R, tile0, ctr);
-            else hipLaunchKernelGGL((batch_kernel<1, 0>), grid, dim3(256), (size_t)b->lds, s, H, R, tile0, ctr);
+            if (dir) hipLaunchKernelGGL((batch_kernel<1, 1>), grid, dim3(256), (size_t)b->lds, s, H, R, tile0, ord, ctr);
+            else hipLaunchKernelGGL((batch_kernel<1, 0>), grid, dim3(256), (size_t)b->lds, s, H, R, tile0, ord, ctr);
         } else {
-            if (dir) hipLaunchKernelGGL((batch_kernel<0, 1>), grid, dim3(256), (size_t)b->lds, s, H, R, tile0, ctr);
-            else hipLaunchKernelGGL((batch_kernel<0, 0>), grid, dim3(256), (size_t)b->lds, s, H, R, tile0, ctr);
+            if (dir) hipLaunchKernelGGL((batch_kernel<0, 1>), grid, dim3(256), (size_t)b->lds, s, H, R, tile0, ord, ctr);
+            else hipLaunchKernelGGL((batch_kernel<0, 0>), grid, dim3(256), (size_t)b->lds, s, H, R, tile0, ord, ctr);
         }
     }
 }
@@ -346,7 +452,8 @@ int launch(mdt_batch_s *b, hipStream_t s)
         return MDT_SUCCESS;
     }
     if (!b->exec || b->graph_grid[0] != g0 || b->graph_grid[1] != g1 || b->graph_policy != b->cfg.policy ||
-        b->graph_buf != b->d_buf || b->graph_lds != b->lds) {
+        b->graph_buf != b->d_buf || b->graph_lds != b->lds || b->graph_ordered != b->cfg.order ||
+        b->graph_order != b->d_order) {
         release_graph(b);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
@@ -366,6 +473,8 @@ int launch(mdt_batch_s *b, hipStream_t s)
         b->graph_policy = b->cfg.policy;
         b->graph_lds = b->lds;
         b->graph_buf = b->d_buf;
+        b->graph_ordered = b->cfg.order;
+        b->graph_order = b->d_order;
     }
     hipError_t e = hipGraphLaunch(b->exec, s);
     if (e != hipSuccess) {
@@ -382,7 +491,7 @@ bool valid_cfg(const mdt_batch_config &c)
     bool tc = c.tile_chunks == 256 || c.tile_chunks == 512 || c.tile_chunks == 1024 || c.tile_chunks == 2048 ||
               c.tile_chunks == 4096;
     return tc && c.wgs_per_cu >= 0 && c.wgs_per_cu <= 16 && (c.policy == 0 || c.policy == 1) &&
-           (c.use_graph == 0 || c.use_graph == 1);
+           (c.use_graph == 0 || c.use_graph == 1) && (c.order == 0 || c.order == 1);
 }
 
 int add_req(mdt_batch b, TypeNode *t, const ReqDesc &d, int32_t lds)
@@ -435,6 +544,8 @@ MDT_API int mdt_batch_free(mdt_batch *pb)
     if (b->d_buf) (void)hipFree(b->d_buf);
     if (b->h_stage) (void)hipHostFree(b->h_stage);
     if (b->d_counter) (void)hipFree(b->d_counter);
+    if (b->d_order) (void)hipFree(b->d_order);
+    if (b->h_order) (void)hipHostFree(b->h_order);
     if (b->staged) (void)hipEventDestroy(b->staged);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     b->magic = 0;
@@ -495,7 +606,11 @@ MDT_API int mdt_batch_add_unpack(mdt_batch b, const void *inbuf, mdt_count insiz
 MDT_API int mdt_batch_set_config(mdt_batch b, const mdt_batch_config *cfg)
 {
     if (!valid_batch(b) || !cfg || !valid_cfg(*cfg)) return MDT_ERR_ARG;
-    if (cfg->tile_chunks != b->cfg.tile_chunks) b->dirty = true;
+    // the tile prefix depends on the tile size, the order table on the order
+    // and (through the XCD slicing) the policy
+    if (cfg->tile_chunks != b->cfg.tile_chunks || cfg->order != b->cfg.order ||
+        (cfg->order && cfg->policy != b->cfg.policy))
+        b->dirty = true;
     b->cfg = *cfg;
     return MDT_SUCCESS;
 }
@@ -526,29 +641,30 @@ MDT_API int mdt_batch_autotune(mdt_batch b, mdt_stream s, mdt_batch_config *best
     const int tiles[] = {256, 1024, 4096};
     const int occ[] = {0, 2, 4, 8};  // 0: one workgroup per tile
     int rc = MDT_SUCCESS;
-    for (int policy = 0; policy < 2 && !rc; policy++)
-        for (int tc : tiles)
-            for (int w : occ) {
-                if (policy == 1 && w == 0) continue;  // nothing to balance with a workgroup per tile
-                mdt_batch_config c{tc, w, policy, keep.use_graph};
-                mdt_batch_set_config(b, &c);
-                rc = launch(b, s->s);  // warm-up (uploads, graph capture)
-                if (rc) break;
-                float ms[3];
-                for (int k = 0; k < 3 && !rc; k++) {
-                    (void)hipEventRecord(e0, s->s);
-                    rc = launch(b, s->s);
-                    (void)hipEventRecord(e1, s->s);
-                    (void)hipEventSynchronize(e1);
-                    (void)hipEventElapsedTime(&ms[k], e0, e1);
+    for (int ord = 0; ord < 2 && !rc; ord++)
+        for (int policy = 0; policy < 2 && !rc; policy++)
+            for (int tc : tiles)
+                for (int w : occ) {
+                    if (policy == 1 && w == 0) continue;  // nothing to balance with a workgroup per tile
+                    mdt_batch_config c{tc, w, policy, keep.use_graph, ord};
+                    mdt_batch_set_config(b, &c);
+                    rc = launch(b, s->s);  // warm-up (uploads, graph capture)
+                    if (rc) break;
+                    float ms[3];
+                    for (int k = 0; k < 3 && !rc; k++) {
+                        (void)hipEventRecord(e0, s->s);
+                        rc = launch(b, s->s);
+                        (void)hipEventRecord(e1, s->s);
+                        (void)hipEventSynchronize(e1);
+                        (void)hipEventElapsedTime(&ms[k], e0, e1);
+                    }
+                    if (rc) break;
+                    std::sort(ms, ms + 3);
+                    if (ms[1] < win_ms) {
+                        win_ms = ms[1];
+                        win = c;
+                    }
                 }
-                if (rc) break;
-                std::sort(ms, ms + 3);
-                if (ms[1] < win_ms) {
-                    win_ms = ms[1];
-                    win = c;
-                }
-            }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) {

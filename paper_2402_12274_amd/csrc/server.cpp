@@ -628,7 +628,7 @@ MDT_API int mdt_server_create(const mdt_server_config *cfg, mdt_server *out)
         st.slots.resize(c.max_inflight);
         for (auto &sl : st.slots) {
             if (mdt_batch_create(&sl.batch) != MDT_SUCCESS) rc = MDT_ERR_NO_MEM;
-            mdt_batch_config bc{1024, 4, 0, 0};
+            mdt_batch_config bc{1024, 4, 0, 0, 0};
             if (sl.batch) mdt_batch_set_config(sl.batch, &bc);
             if (hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess) rc = MDT_ERR_HIP;
         }

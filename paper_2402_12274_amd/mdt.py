@@ -52,7 +52,8 @@ class Iov(C.Structure):
 
 
 class BatchConfig(C.Structure):
-    _fields_ = [("tile_chunks", C.c_int), ("wgs_per_cu", C.c_int), ("policy", C.c_int), ("use_graph", C.c_int)]
+    _fields_ = [("tile_chunks", C.c_int), ("wgs_per_cu", C.c_int), ("policy", C.c_int), ("use_graph", C.c_int),
+                ("order", C.c_int)]
 
 
 class LayoutInfo(C.Structure):
