@@ -10,9 +10,18 @@ read once and written once by pack, and again by unpack: 4 x packed bytes
 per step), with all inputs resident in device memory before timing starts.
 
 Other workloads (--workload): particles (struct records x 4M), hindexed (1M
-irregular blocks in 2 GiB), contig (1 GiB contiguous), small (the 1024-
-element vector).  --mode batched runs each direction of a step as one
-persistent batched launch instead of one launch per face.
+irregular blocks in 2 GiB), contig (1 GiB contiguous), rows (an interior
+block of an 8192^2 float64 matrix), small (the 1024-element vector), serve
+(the serving trace, served vs per-request) and batch4096 (4096 requests in
+one launch vs 4096 launches).  --mode batched (the default) runs each
+direction of a step as one batched launch (autotuned); --mode plain launches
+once per request, and batched runs report that as "per_request" too.
+
+roofline: the launches are queued back to back between one pair of HIP
+events on the launch stream; the region's device time over its launch count
+is the average launch duration, and achieved = algorithmic bytes per launch
+over it.  traffic: measured HBM bytes per launch from the committed counter
+summary (profiles/hbm_traffic.md) when it was taken on the current sources.
 
 Prints one JSON line.  Run with no flags for the default single-GPU run.
 """
@@ -33,6 +42,41 @@ sys.path.insert(0, HERE)
 from paper_2402_12274_amd import inputs  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
+TRAFFIC_TABLE = os.path.join(HERE, "profiles", "hbm_traffic.md")
+
+
+def kernel_sources_sha():
+    """sha256 over the library's sources and header: a measured HBM traffic
+    figure holds only for the sources it was measured on."""
+    import hashlib
+
+    h = hashlib.sha256()
+    src = os.path.join(HERE, "paper_2402_12274_amd", "csrc")
+    for name in sorted(os.listdir(src)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(src, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    with open(os.path.join(HERE, "include", "mdt.h"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain
+    copy's readings), or None when there is none for the current sources."""
+    if not os.path.exists(TRAFFIC_TABLE):
+        return None
+    sha = kernel_sources_sha()
+    with open(TRAFFIC_TABLE) as f:
+        for line in f:
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 6 and cells[0] == workload and cells[1] == kernel and cells[-1] == sha:
+                try:
+                    return int(cells[4])
+                except ValueError:
+                    return None
+    return None
 METRIC = "pack+unpack HBM GB/s vs peak; p50/p99 latency, batched vs per-request"
 
 
@@ -387,74 +431,51 @@ def main():
             bp.set_config(bp0.get_config())
             bu.set_config(bu0.get_config())
 
-    # HIP events around every launch on the launch stream, grouped by kernel
-    # (batched: one persistent kernel for both directions; plain: per direction)
-    ev_log = {}
-
-    def log(name, e0, e1, nbytes):
-        ev_log.setdefault(name, []).append((e0, e1, nbytes))
-
-    def step(r, timed, batched):
+    # One HIP event pair on the launch stream brackets the timed steps (events
+    # between launches would add host work the GPU then waits for); launches
+    # are queued back to back, so the region's device time over its launch
+    # count is the average launch duration.
+    def step(r, batched):
         if batched:
             bp, bu = batches[r]
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e2 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
             bp.launch(ms)
-            e1.record(stream)
             bu.launch(ms)
-            e2.record(stream)
-            if timed:
-                log("batch_kernel (pack and unpack launches)", e0, e1, sum(sizes))
-                log("batch_kernel (pack and unpack launches)", e1, e2, sum(sizes))
             return
         for (label, t, count), out, s in zip(types, packed[r], sizes):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
             mdt.mdt_pack_enqueue(srcs[r].data_ptr(), count, t, 0, out.data_ptr(), -1, ms)
-            e1.record(stream)
-            if timed:
-                log("pack launches", e0, e1, s)
         for (label, t, count), out, s in zip(types, packed[r], sizes):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
             mdt.mdt_unpack_enqueue(out.data_ptr(), s, dsts[r].data_ptr(), count, t, 0, ms)
-            e1.record(stream)
-            if timed:
-                log("unpack launches", e0, e1, s)
 
-    def timed_run(batched, record):
-        for i in range(args.warmup):
-            step(i % R, False, batched)
+    def timed_run(batched):
+        # every rotating copy runs once before timing (its first launch
+        # uploads descriptors or captures a graph)
+        for i in range(max(args.warmup, R)):
+            step(i % R, batched)
         torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
+        e0.record(stream)
         for i in range(args.steps):
-            step(i % R, record, batched)
+            step(i % R, batched)
+        e1.record(stream)
         torch.cuda.synchronize()
-        return time.perf_counter() - t0
+        return time.perf_counter() - t0, e0.elapsed_time(e1) * 1e-3
 
-    dt = timed_run(batches is not None, True)
+    batched = batches is not None
+    dt, dev_s = timed_run(batched)
     value = step_bytes * args.steps / dt / 1e9
+    launches_per_step = 2 if batched else 2 * len(types)
+    dom = "batch_kernel (pack and unpack launches)" if batched else "pack and unpack launches"
+    avg_dur = dev_s / (launches_per_step * args.steps)
+    bytes_per_launch = step_bytes / launches_per_step
+    achieved = bytes_per_launch / avg_dur / 1e9 if avg_dur > 0 else 0.0
     other = None
-    if batches is not None:
-        dt_plain = timed_run(False, False)
+    if batched:
+        dt_plain, _ = timed_run(False)
         other = {"mode": "plain (one launch per request)", "value": round(step_bytes * args.steps / dt_plain / 1e9, 2),
                  "ms_per_step": round(dt_plain / args.steps * 1e3, 4)}
     copy_ceiling = copy_ceiling_gbs(torch, dev)
-    # dominant kernel: the one with the larger total kernel time
-    per = {}
-    for k, lst in ev_log.items():
-        durs = [a.elapsed_time(b) * 1e-3 for a, b, _ in lst]
-        per[k] = dict(total=sum(durs), n=len(durs), bytes=sum(2 * s for _, _, s in lst))
-    dom = max(per, key=lambda k: per[k]["total"])
-    d = per[dom]
-    avg_dur = d["total"] / max(1, d["n"])
-    bytes_per_launch = d["bytes"] / max(1, d["n"])
-    achieved = bytes_per_launch / avg_dur / 1e9 if avg_dur > 0 else 0.0
-
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -473,7 +494,8 @@ def main():
                    "frac_of_peak_value": round(value / PEAK_HBM_GBS, 4),
                    "device_copy_ceiling_GBps": copy_ceiling, "autotuned": tuned},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": measured_traffic(args.workload + "/" + args.mode, dom),
                      "kernel": dom,
                      "avg_launch_us": round(avg_dur * 1e6, 2), "bytes_per_launch": int(bytes_per_launch)},
     }

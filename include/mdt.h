@@ -297,9 +297,11 @@ typedef struct mdt_batch_config {
 } mdt_batch_config;
 MDT_API int mdt_batch_set_config(mdt_batch b, const mdt_batch_config *cfg);
 MDT_API int mdt_batch_get_config(mdt_batch b, mdt_batch_config *cfg);
-/* Time candidate configurations on the batch as it stands (running it
- * several times; destinations are overwritten with the same bytes) and keep
- * the fastest.  *best may be NULL. */
+/* Time candidate configurations on the batch as it stands -- tile size,
+ * workgroups per CU, split policy, tile order, and graph replay against
+ * direct launches -- running it several times (destinations are
+ * overwritten with the same bytes), and keep the fastest.  *best may be
+ * NULL. */
 MDT_API int mdt_batch_autotune(mdt_batch b, mdt_stream s, mdt_batch_config *best);
 MDT_API int mdt_batch_launch(mdt_batch b, mdt_stream s, mdt_request *req);
 

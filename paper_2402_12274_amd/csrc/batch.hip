@@ -1,19 +1,22 @@
-// batch.hip -- many pack/unpack requests in one persistent launch.
+// batch.hip -- many pack/unpack requests in one launch per direction.
 //
 // Launching one kernel per request costs a few microseconds of host and
 // dispatch time each; thousands of small requests are then bound by launch
 // overhead, not by HBM (MPIX Streams, Background: launch and synchronisation
 // cost is a key performance factor).  A batch lowers every request into
-// tiles of consecutive 16-byte chunks, lays the request descriptors and the
-// per-request first-tile prefix out in device memory, and runs one
-// persistent grid (workgroups per CU x CUs) that pulls tiles either in a
-// static strided order or from an atomic counter.  Each tile finds its
-// request by binary search over the prefix and runs exactly the chunk body
-// of the single-request kernels, so every byte is identical to the request
-// run alone.  The launch (counter reset + persistent kernel) is captured
-// once in a HIP graph and replayed; descriptors are uploaded in stream order
-// only when the batch changed.  An autotuner times tile size, occupancy and
-// split policy on the batch itself and keeps the fastest.
+// tiles of consecutive 16-byte chunks, lays the request descriptors (pack
+// requests first) and the per-request first-tile prefix out in device
+// memory, and runs one grid per direction: persistent (workgroups per CU x
+// CUs) pulling tiles in a static strided order or from an atomic counter, or
+// one workgroup per tile.  Tiles run in request order or in the order of the
+// typed address they start at (requests that share cache lines then run
+// together, each XCD taking one slice).  Each tile finds its request by
+// binary search over the prefix, reads the request's layout program through
+// the scalar cache, and runs exactly the tile bodies of the single-request
+// kernels, so every byte is identical to the request run alone.  The launch
+// can be captured once in a HIP graph and replayed; descriptors are uploaded
+// in stream order only when the batch changed.  An autotuner times these
+// choices on the batch itself and keeps the fastest.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -641,30 +644,31 @@ MDT_API int mdt_batch_autotune(mdt_batch b, mdt_stream s, mdt_batch_config *best
     const int tiles[] = {256, 1024, 4096};
     const int occ[] = {0, 2, 4, 8};  // 0: one workgroup per tile
     int rc = MDT_SUCCESS;
-    for (int ord = 0; ord < 2 && !rc; ord++)
-        for (int policy = 0; policy < 2 && !rc; policy++)
-            for (int tc : tiles)
-                for (int w : occ) {
-                    if (policy == 1 && w == 0) continue;  // nothing to balance with a workgroup per tile
-                    mdt_batch_config c{tc, w, policy, keep.use_graph, ord};
-                    mdt_batch_set_config(b, &c);
-                    rc = launch(b, s->s);  // warm-up (uploads, graph capture)
-                    if (rc) break;
-                    float ms[3];
-                    for (int k = 0; k < 3 && !rc; k++) {
-                        (void)hipEventRecord(e0, s->s);
-                        rc = launch(b, s->s);
-                        (void)hipEventRecord(e1, s->s);
-                        (void)hipEventSynchronize(e1);
-                        (void)hipEventElapsedTime(&ms[k], e0, e1);
+    for (int graph = 0; graph < 2 && !rc; graph++)
+        for (int ord = 0; ord < 2 && !rc; ord++)
+            for (int policy = 0; policy < 2 && !rc; policy++)
+                for (int tc : tiles)
+                    for (int w : occ) {
+                        if (policy == 1 && w == 0) continue;  // nothing to balance with a workgroup per tile
+                        mdt_batch_config c{tc, w, policy, graph, ord};
+                        mdt_batch_set_config(b, &c);
+                        rc = launch(b, s->s);  // warm-up (uploads, graph capture)
+                        if (rc) break;
+                        float ms[3];
+                        for (int k = 0; k < 3 && !rc; k++) {
+                            (void)hipEventRecord(e0, s->s);
+                            rc = launch(b, s->s);
+                            (void)hipEventRecord(e1, s->s);
+                            (void)hipEventSynchronize(e1);
+                            (void)hipEventElapsedTime(&ms[k], e0, e1);
+                        }
+                        if (rc) break;
+                        std::sort(ms, ms + 3);
+                        if (ms[1] < win_ms) {
+                            win_ms = ms[1];
+                            win = c;
+                        }
                     }
-                    if (rc) break;
-                    std::sort(ms, ms + 3);
-                    if (ms[1] < win_ms) {
-                        win_ms = ms[1];
-                        win = c;
-                    }
-                }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) {
