@@ -37,8 +37,16 @@ struct ReqDesc {
     uint8_t *packed;
     int64_t off, nbytes, head, nchunks;
     int32_t unpack, kind;
-    int32_t elem1, dense;
+    int32_t elem1, body;  // BODY_DENSE, BODY_RUNS or BODY_CHUNK
 };
+
+// Tile bodies a batch kernel carries (a bit set): a kernel compiled for one
+// body needs only that body's registers, so a direction whose requests all
+// take one path runs at that path's occupancy.
+constexpr int BODY_DENSE = 1;  // record view, LDS-staged
+constexpr int BODY_RUNS = 2;   // run tables, LDS-cached group slice
+constexpr int BODY_CHUNK = 4;  // chunk path
+constexpr int BODY_ALL = 7;
 
 // Descriptors are stored pack requests first, so each direction's tiles
 // form one range: [0, ntiles_dir[0]) for pack, then unpack.
@@ -51,30 +59,42 @@ struct BatchHeader {
 };
 
 // Chunks [c0, cend) of one request, with the single-request bodies.
-__device__ __forceinline__ void run_tile(const DevLayout &L, const XferArgs &A, const int unpack, int dense, int kind,
-                                         int64_t c0, int64_t cend, uint8_t *lds_dyn)
+template <int UNPACK, int BODY>
+__device__ __forceinline__ void run_tile(const DevLayout &L, const XferArgs &A, int body, int kind, int64_t c0,
+                                         int64_t cend, uint8_t *lds_dyn)
 {
-    if (dense) {
+    if ((BODY & BODY_DENSE) && body == BODY_DENSE) {
         // sub-tiles sized to the type's LDS budget; LDS is reused between them
         const int64_t st = L.rec.tile_chunks;
         for (int64_t s0 = c0; s0 < cend; s0 += st) {
             int64_t s1 = s0 + st < cend ? s0 + st : cend;
-            if (unpack) dense_unpack_tile(L, A, s0, s1, lds_dyn);
+            if (UNPACK) dense_unpack_tile(L, A, s0, s1, lds_dyn);
             else dense_pack_tile(L, A, s0, s1, lds_dyn);
             __syncthreads();
         }
         return;
     }
-    for (int64_t s0 = c0; s0 < cend; s0 += 1024) {
-        int64_t s1 = s0 + 1024 < cend ? s0 + 1024 : cend;
-        if (unpack) {
-            if (kind == KIND_CONTIG) unpack_tile4<KIND_CONTIG>(L, A, s0, s1);
-            else if (kind == KIND_SINGLE) unpack_tile4<KIND_SINGLE>(L, A, s0, s1);
-            else unpack_tile4<KIND_MULTI>(L, A, s0, s1);
-        } else {
-            if (kind == KIND_CONTIG) pack_tile4<KIND_CONTIG>(L, A, s0, s1);
-            else if (kind == KIND_SINGLE) pack_tile4<KIND_SINGLE>(L, A, s0, s1);
-            else pack_tile4<KIND_MULTI>(L, A, s0, s1);
+    if ((BODY & BODY_RUNS) && body == BODY_RUNS) {
+        RunsCache &C = *reinterpret_cast<RunsCache *>(lds_dyn);
+        for (int64_t s0 = c0; s0 < cend; s0 += 1024) {
+            int64_t s1 = s0 + 1024 < cend ? s0 + 1024 : cend;
+            runs_tile<UNPACK != 0>(L, A, s0, s1, C);
+            __syncthreads();  // the cache is refilled for the next sub-tile
+        }
+        return;
+    }
+    if (BODY & BODY_CHUNK) {
+        for (int64_t s0 = c0; s0 < cend; s0 += 1024) {
+            int64_t s1 = s0 + 1024 < cend ? s0 + 1024 : cend;
+            if (UNPACK) {
+                if (kind == KIND_CONTIG) unpack_tile4<KIND_CONTIG>(L, A, s0, s1);
+                else if (kind == KIND_SINGLE) unpack_tile4<KIND_SINGLE>(L, A, s0, s1);
+                else unpack_tile4<KIND_MULTI>(L, A, s0, s1);
+            } else {
+                if (kind == KIND_CONTIG) pack_tile4<KIND_CONTIG>(L, A, s0, s1);
+                else if (kind == KIND_SINGLE) pack_tile4<KIND_SINGLE>(L, A, s0, s1);
+                else pack_tile4<KIND_MULTI>(L, A, s0, s1);
+            }
         }
     }
 }
@@ -103,7 +123,7 @@ __device__ __forceinline__ const DevLayout &const_layout(uint64_t addr)
 // gridDim.x (with one workgroup per tile, each workgroup takes one tile);
 // POLICY 1: tiles taken from an atomic counter.  Every workgroup leaves the
 // loop once the tile index passes the direction's last tile.
-template <int POLICY, int UNPACK>
+template <int POLICY, int UNPACK, int BODY>
 __global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restrict__ H,
                                                     const ReqDesc *__restrict__ R,
                                                     const int64_t *__restrict__ tile0,
@@ -149,7 +169,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restric
             A.elem1 = D.elem1;
             int64_t c0 = (tile - tile0[lo]) * T;
             int64_t cend = c0 + T < D.nchunks ? c0 + T : D.nchunks;
-            run_tile(L, A, UNPACK, D.dense, D.kind, c0, cend, lds_dyn);
+            run_tile<UNPACK, BODY>(L, A, D.body, D.kind, c0, cend, lds_dyn);
         }
         if (POLICY == 0) {
             t += gridDim.x;
@@ -171,7 +191,7 @@ constexpr uint32_t BATCH_MAGIC = 0x6d647442u;
 struct BatchReq {
     TypeNode *type;  // retained
     ReqDesc d;
-    int32_t lds;     // dynamic LDS the request needs on the dense path
+    int32_t lds;     // dynamic LDS the request's body needs
 };
 
 struct mdt_batch_s {
@@ -194,13 +214,15 @@ struct mdt_batch_s {
     int32_t *h_order = nullptr;
     size_t order_cap = 0;
     bool staged_order = false;  // the uploaded table matches the current schedule
-    int32_t lds = 0;  // dynamic LDS of the persistent kernel (largest dense request)
+    int32_t lds_dir[2] = {0, 0};   // dynamic LDS per direction (the largest request's need)
+    int32_t body_dir[2] = {0, 0};  // tile bodies each direction's requests take
     int32_t dirs = 0; // bit 0: has pack requests, bit 1: has unpack requests
     // captured launch
     hipGraphExec_t exec = nullptr;
     hipStream_t cap_stream = nullptr;
     int graph_grid[2] = {-1, -1};
-    int graph_policy = -1, graph_lds = -1, graph_ordered = -1;
+    int graph_policy = -1, graph_ordered = -1;
+    int32_t graph_lds[2] = {-1, -1}, graph_body[2] = {-1, -1};
     uint8_t *graph_buf = nullptr;
     int32_t *graph_order = nullptr;
 };
@@ -363,7 +385,8 @@ int stage(mdt_batch_s *b, hipStream_t s)
     int64_t *tile0 = (int64_t *)(b->h_stage + tile_off(b->cap));
     int64_t acc = 0;
     size_t k = 0;
-    b->lds = 0;
+    b->lds_dir[0] = b->lds_dir[1] = 0;
+    b->body_dir[0] = b->body_dir[1] = 0;
     b->dirs = 0;
     // pack requests first, then unpack, each in the order they were added
     for (int dir = 0; dir < 2; dir++) {
@@ -371,7 +394,8 @@ int stage(mdt_batch_s *b, hipStream_t s)
         for (size_t i = 0; i < b->reqs.size(); i++) {
             if (b->reqs[i].d.unpack != dir) continue;
             D[k] = b->reqs[i].d;
-            if (D[k].dense) b->lds = std::max(b->lds, b->reqs[i].lds);
+            b->lds_dir[dir] = std::max(b->lds_dir[dir], b->reqs[i].lds);
+            b->body_dir[dir] |= D[k].body;
             tile0[k] = acc;
             acc += (b->reqs[i].d.nchunks + T - 1) / T;
             H.nreq_dir[dir]++;
@@ -414,25 +438,42 @@ int grid_of(const mdt_batch_s *b, int dir)
     return (int)std::min<int64_t>(std::max<int64_t>(1, g), INT32_MAX);
 }
 
-void enqueue_kernels(mdt_batch_s *b, hipStream_t s)
+template <int POLICY, int UNPACK, int BODY>
+void launch_one(mdt_batch_s *b, hipStream_t s, dim3 grid, size_t lds, unsigned long long *ctr)
 {
     const BatchHeader *H = (const BatchHeader *)b->d_buf;
     const ReqDesc *R = (const ReqDesc *)(b->d_buf + desc_off());
     const int64_t *tile0 = (const int64_t *)(b->d_buf + tile_off(b->cap));
-    const int32_t *ord = b->d_order;
-    // one kernel per direction: a mixed batch runs its pack tiles and its
-    // unpack tiles as two launches (each kernel skips the other direction)
+    hipLaunchKernelGGL((batch_kernel<POLICY, UNPACK, BODY>), grid, dim3(256), lds, s, H, R, tile0, b->d_order, ctr);
+}
+
+template <int POLICY, int UNPACK>
+void launch_dir(mdt_batch_s *b, hipStream_t s, dim3 grid, size_t lds, unsigned long long *ctr, int body)
+{
+    // a kernel with only the body the direction needs, else one with all
+    if (body == BODY_DENSE) launch_one<POLICY, UNPACK, BODY_DENSE>(b, s, grid, lds, ctr);
+    else if (body == BODY_RUNS) launch_one<POLICY, UNPACK, BODY_RUNS>(b, s, grid, lds, ctr);
+    else if (body == BODY_CHUNK) launch_one<POLICY, UNPACK, BODY_CHUNK>(b, s, grid, lds, ctr);
+    else launch_one<POLICY, UNPACK, BODY_ALL>(b, s, grid, lds, ctr);
+}
+
+void enqueue_kernels(mdt_batch_s *b, hipStream_t s)
+{
+    // one kernel per direction: a mixed batch runs its pack tiles, then its
+    // unpack tiles
     for (int dir = 0; dir < 2; dir++) {
         if (!(b->dirs & (1 << dir))) continue;
         const dim3 grid((unsigned)grid_of(b, dir));
+        const size_t lds = (size_t)b->lds_dir[dir];
+        const int body = b->body_dir[dir];
         unsigned long long *ctr = b->d_counter + dir;
         if (b->cfg.policy == 1) {
             hipLaunchKernelGGL(batch_counter_reset, dim3(1), dim3(1), 0, s, ctr);
-            if (dir) hipLaunchKernelGGL((batch_kernel<1, 1>), grid, dim3(256), (size_t)b->lds, s, H, R, tile0, ord, ctr);
-            else hipLaunchKernelGGL((batch_kernel<1, 0>), grid, dim3(256), (size_t)b->lds, s, H, R, tile0, ord, ctr);
+            if (dir) launch_dir<1, 1>(b, s, grid, lds, ctr, body);
+            else launch_dir<1, 0>(b, s, grid, lds, ctr, body);
         } else {
-            if (dir) hipLaunchKernelGGL((batch_kernel<0, 1>), grid, dim3(256), (size_t)b->lds, s, H, R, tile0, ord, ctr);
-            else hipLaunchKernelGGL((batch_kernel<0, 0>), grid, dim3(256), (size_t)b->lds, s, H, R, tile0, ord, ctr);
+            if (dir) launch_dir<0, 1>(b, s, grid, lds, ctr, body);
+            else launch_dir<0, 0>(b, s, grid, lds, ctr, body);
         }
     }
 }
@@ -455,7 +496,8 @@ int launch(mdt_batch_s *b, hipStream_t s)
         return MDT_SUCCESS;
     }
     if (!b->exec || b->graph_grid[0] != g0 || b->graph_grid[1] != g1 || b->graph_policy != b->cfg.policy ||
-        b->graph_buf != b->d_buf || b->graph_lds != b->lds || b->graph_ordered != b->cfg.order ||
+        b->graph_buf != b->d_buf || b->graph_lds[0] != b->lds_dir[0] || b->graph_lds[1] != b->lds_dir[1] ||
+        b->graph_body[0] != b->body_dir[0] || b->graph_body[1] != b->body_dir[1] || b->graph_ordered != b->cfg.order ||
         b->graph_order != b->d_order) {
         release_graph(b);
         hipGraph_t g = nullptr;
@@ -474,7 +516,10 @@ int launch(mdt_batch_s *b, hipStream_t s)
         b->graph_grid[0] = g0;
         b->graph_grid[1] = g1;
         b->graph_policy = b->cfg.policy;
-        b->graph_lds = b->lds;
+        for (int d = 0; d < 2; d++) {
+            b->graph_lds[d] = b->lds_dir[d];
+            b->graph_body[d] = b->body_dir[d];
+        }
         b->graph_buf = b->d_buf;
         b->graph_ordered = b->cfg.order;
         b->graph_order = b->d_order;
@@ -495,6 +540,22 @@ bool valid_cfg(const mdt_batch_config &c)
               c.tile_chunks == 4096;
     return tc && c.wgs_per_cu >= 0 && c.wgs_per_cu <= 16 && (c.policy == 0 || c.policy == 1) &&
            (c.use_graph == 0 || c.use_graph == 1) && (c.order == 0 || c.order == 1);
+}
+
+// The tile body a request takes (the same choice as the single-request
+// launch) and the dynamic LDS it needs.
+int body_of(const DevLayout &L, const XferArgs &A, bool unpack, int32_t *lds)
+{
+    if (use_dense(L, A, unpack)) {
+        *lds = L.rec.lds_bytes;
+        return BODY_DENSE;
+    }
+    if (use_runs(L)) {
+        *lds = (int32_t)sizeof(RunsCache);
+        return BODY_RUNS;
+    }
+    *lds = 0;
+    return BODY_CHUNK;
 }
 
 int add_req(mdt_batch b, TypeNode *t, const ReqDesc &d, int32_t lds)
@@ -572,9 +633,10 @@ MDT_API int mdt_batch_add_pack(mdt_batch b, const void *inbuf, mdt_count incount
     if (n > 0) {
         XferArgs A = make_args(inbuf, outbuf, inoffset, n);
         A.elem1 = A.off + A.nbytes <= D->lay.size;
-        int dense = use_dense(D->lay, A, false);
-        ReqDesc d{(uint64_t)(uintptr_t)D->d_lay, A.typed, A.packed, A.off, A.nbytes, A.head, A.nchunks, 0, D->lay.kind, A.elem1, dense};
-        rc = add_req(b, reinterpret_cast<TypeNode *>(t), d, dense ? D->lay.rec.lds_bytes : 0);
+        int32_t lds = 0;
+        const int body = body_of(D->lay, A, false, &lds);
+        ReqDesc d{(uint64_t)(uintptr_t)D->d_lay, A.typed, A.packed, A.off, A.nbytes, A.head, A.nchunks, 0, D->lay.kind, A.elem1, body};
+        rc = add_req(b, reinterpret_cast<TypeNode *>(t), d, lds);
         if (rc) return rc;
     }
     *actual_pack_bytes = n;
@@ -597,9 +659,10 @@ MDT_API int mdt_batch_add_unpack(mdt_batch b, const void *inbuf, mdt_count insiz
     if (insize > 0) {
         XferArgs A = make_args(outbuf, const_cast<void *>(inbuf), outoffset, insize);
         A.elem1 = A.off + A.nbytes <= D->lay.size;
-        int dense = use_dense(D->lay, A, true);
-        ReqDesc d{(uint64_t)(uintptr_t)D->d_lay, A.typed, A.packed, A.off, A.nbytes, A.head, A.nchunks, 1, D->lay.kind, A.elem1, dense};
-        rc = add_req(b, reinterpret_cast<TypeNode *>(t), d, dense ? D->lay.rec.lds_bytes : 0);
+        int32_t lds = 0;
+        const int body = body_of(D->lay, A, true, &lds);
+        ReqDesc d{(uint64_t)(uintptr_t)D->d_lay, A.typed, A.packed, A.off, A.nbytes, A.head, A.nchunks, 1, D->lay.kind, A.elem1, body};
+        rc = add_req(b, reinterpret_cast<TypeNode *>(t), d, lds);
         if (rc) return rc;
     }
     *actual_unpack_bytes = insize;

@@ -27,5 +27,7 @@ int launch_flatten(Compiled *c, DeviceTables *d, int64_t off, int64_t m, mdt_iov
 int64_t default_tile_chunks(int64_t nchunks);
 // the dense record path applies to this request
 bool use_dense(const DevLayout &L, const XferArgs &A, bool unpack);
+// the run-table kernel (LDS-cached group slice) applies
+bool use_runs(const DevLayout &L);
 
 }  // namespace mdt

@@ -282,6 +282,8 @@ bool use_dense(const DevLayout &L, const XferArgs &A, bool unpack)
     return !unpack || R.unpack_ok;
 }
 
+bool use_runs(const DevLayout &L) { return L.kind == KIND_MULTI && L.runs_only && runs_enabled(); }
+
 int launch_xfer(const DevLayout &L, const XferArgs &A0, bool unpack, hipStream_t s)
 {
     if (A0.nbytes == 0 || L.kind == KIND_EMPTY) return MDT_SUCCESS;
@@ -296,7 +298,7 @@ int launch_xfer(const DevLayout &L, const XferArgs &A0, bool unpack, hipStream_t
         HIPCHK(hipGetLastError());
         return MDT_SUCCESS;
     }
-    if (L.kind == KIND_MULTI && L.runs_only && runs_enabled()) {
+    if (use_runs(L)) {
         A.tile_chunks = 1024;
         int64_t grid = launch_grid((A.nchunks + A.tile_chunks - 1) / A.tile_chunks);
         if (unpack) hipLaunchKernelGGL(runs_kernel<true>, dim3((unsigned)grid), dim3(256), 0, s, L, A);
