@@ -221,10 +221,8 @@ __device__ __forceinline__ void unpack_chunk(const DevLayout &L, const XferArgs 
     }
 }
 
-// A lane's chunks c0 + lane + 256k (k < 4) of a tile, loads first: every
-// chunk whose 16 bytes lie in one run is loaded before any store is issued,
-// so up to four gathers per lane are in flight at once.  Other chunks take
-// the general body.
+// Load chunk c whole when its bytes lie in one run or in two dword-aligned
+// runs; false when it needs the general body (or lies outside the tile).
 template <int KIND>
 __device__ __forceinline__ bool pack_first(const DevLayout &L, const XferArgs &A, int64_t c, int64_t cend, V4 &acc)
 {
@@ -234,6 +232,22 @@ __device__ __forceinline__ bool pack_first(const DevLayout &L, const XferArgs &A
         if (l.rem >= 16) {
             acc = load16(A.typed + l.addr);
             return true;
+        }
+        // two runs split on a dword boundary, both dword aligned (blocks of
+        // float64 or int32 at a stride): four independent dword loads, each
+        // from whichever run holds that word
+        const uintptr_t a1 = (uintptr_t)(A.typed + l.addr);
+        const int t1 = (int)l.rem;
+        if (((a1 | (uintptr_t)t1) & 3) == 0) {
+            Loc l2 = locate<KIND>(L, (uint64_t)(A.off + lo + t1), A.elem1);
+            const uintptr_t a2 = (uintptr_t)(A.typed + l2.addr) - (uintptr_t)t1;  // chunk byte j of run 2 at a2 + j
+            if (l2.rem >= 16 - t1 && (a2 & 3) == 0) {
+                acc.w0 = *gptr((const uint32_t *)(0 < t1 ? a1 : a2));
+                acc.w1 = *gptr((const uint32_t *)(4 < t1 ? a1 + 4 : a2 + 4));
+                acc.w2 = *gptr((const uint32_t *)(8 < t1 ? a1 + 8 : a2 + 8));
+                acc.w3 = *gptr((const uint32_t *)(12 < t1 ? a1 + 12 : a2 + 12));
+                return true;
+            }
         }
     }
     return false;
@@ -325,9 +339,10 @@ __device__ __forceinline__ void unpack_tile_run(const XferArgs &A, int64_t c0, i
 }
 
 // A lane's chunks c0 + lane + 256k (k < 4) of a tile, loads first: every
-// chunk whose 16 bytes lie in one run is loaded before any store is issued,
-// so up to four gathers per lane are in flight at once.  The other chunks
-// then take the general body, one at a time.
+// chunk whose 16 bytes lie in one run, or in two dword-aligned runs, is
+// loaded before any store is issued, so up to four gathers per lane are in
+// flight at once.  The other chunks then take the general body, one at a
+// time.  A tile that lies inside one run is a plain copy.
 template <int KIND>
 __device__ __forceinline__ void pack_tile4(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t cend)
 {
