@@ -195,6 +195,52 @@ def test_batch_mixed_directions(env):
             assert first_diff(to_host(dsts[i]), dexp[i]) is None, (wgs, i)
 
 
+def test_batch_single_body_kernels(env):
+    # batches whose requests all take one tile body run a kernel compiled for
+    # that body only: run tables (hindexed of bytes), chunk path (faces),
+    # record path (particles); pack and unpack must equal the oracle
+    torch, mdt = env
+    lens, disps = inputs.hindexed_blocks(nblocks=30000, span=1 << 22, seed=21)
+    groups = {
+        "runs": [inputs.hindexed_type(lens, disps)],
+        "chunk": [inputs.halo_face(64, 1, 2, "lo"), inputs.halo_face(64, 4, 0, "hi"), inputs.halo_face(64, 2, 1, "lo")],
+        "records": [inputs.particle_struct()],
+    }
+    counts = {"runs": 2, "chunk": 1, "records": 7001}
+    expect_body = {"runs": (3, 0), "chunk": (2, 0), "records": (2, 1)}
+    ms = mdt.Stream(torch.cuda.current_stream().cuda_stream)
+    for name, specs in groups.items():
+        types = [mdt.build_type(sp) for sp in specs]
+        kind, rec = expect_body[name]
+        assert all(t.layout_info()["kind"] == kind and t.layout_info()["records"] == rec for t in types), name
+        for wgs, order in ((0, 0), (4, 1)):
+            note(f"single-body batch {name} wgs={wgs} order={order}")
+            bp, bu = mdt.Batch(), mdt.Batch()
+            keep = []
+            for i, (sp, t) in enumerate(zip(specs, types)):
+                o = obuild(sp)
+                a = o.attrs()
+                c = counts[name]
+                nb = (c - 1) * a["extent"] + a["true_ub"] + 8
+                h = inputs.random_bytes(nb, seed=70 + i)
+                full = o.pack(h, 0, c)
+                src, out = to_dev(h), zeros_dev(full.size, 0)
+                canary = np.full(nb, 0x21, np.uint8)
+                exp_u = canary.copy()
+                o.unpack(full, exp_u, 0, c)
+                pk, dst = to_dev(full), to_dev(canary)
+                bp.add_pack(src.data_ptr(), c, t, 0, out.data_ptr(), -1)
+                bu.add_unpack(pk.data_ptr(), full.size, dst.data_ptr(), c, t, 0)
+                keep.append((src, out, full, pk, dst, exp_u))
+            for b in (bp, bu):
+                b.set_config(mdt.BatchConfig(1024, wgs, 0, 1, order))
+                b.launch(ms)
+            torch.cuda.synchronize()
+            for src, out, full, pk, dst, exp_u in keep:
+                assert first_diff(to_host(out), full) is None, name
+                assert first_diff(to_host(dst), exp_u) is None, name
+
+
 def test_server_mix_equals_alone(env):
     torch, mdt = env
     n_face, vec_count = 96, 1 << 13
