@@ -63,6 +63,13 @@ const int64_t BATCH_BYTES = [] {
     long long v = e && *e ? atoll(e) : (8ll << 20);
     return (int64_t)(v > 0 ? v : (8ll << 20));
 }();
+// Requests at least this large (packed bytes) are launched on their own
+// hardware queue, in order (MDT_SERVER_LARGE_BYTES).
+const int64_t LARGE_BYTES = [] {
+    const char *e = getenv("MDT_SERVER_LARGE_BYTES");
+    long long v = e && *e ? atoll(e) : (4ll << 20);
+    return (int64_t)(v > 0 ? v : (4ll << 20));
+}();
 // Hardware queues a process's streams are spread over (the runtime's
 // GPU_MAX_HW_QUEUES, 4 unless set).
 const int HW_QUEUES = [] {
@@ -204,7 +211,7 @@ struct mdt_server_s {
     int inject_fail = 0;
     std::atomic<bool> run_thread{false};
     bool draining = false;       // shutdown: admit regardless of the budget
-    std::atomic<int64_t> work{0};   // queued + admitted + released items + launches in flight
+    std::atomic<int64_t> work{0};   // queued + admitted items + launches in flight
     std::atomic<int> launches_inflight{0};
     std::atomic<double> last_reap{0.0};  // time of the last completion query round
     std::condition_variable wake;  // submit -> idle progress thread
@@ -387,18 +394,32 @@ int progress_locked(mdt_server s)
         const int hwq = std::max(1, std::min(nst, HW_QUEUES));
         int64_t qbytes[64] = {0};
         for (int i = 0; i < nst; i++) qbytes[i % hwq] += s->streams[(size_t)i].bytes;
+        // large requests take hardware queue 0 in arrival order (two large
+        // requests then finish one after the other instead of both late);
+        // the others use the remaining queues
+        const bool large = s->admitted.front()->nbytes >= LARGE_BYTES;
         StreamState *best = nullptr;
         int64_t best_load = 0;
         for (int i = 0; i < nst; i++) {
             StreamState &st = s->streams[(size_t)i];
             if (st.busy >= (int)st.slots.size()) continue;
+            if (hwq > 1 && (i % hwq == 0) != large) continue;
             const int64_t load = qbytes[i % hwq];
             if (!best || load < best_load || (load == best_load && st.busy < best->busy)) {
                 best = &st;
                 best_load = load;
             }
         }
-        if (!best) break;
+        if (!best) {
+            // the large queue is full: let a small request behind go first
+            auto it = std::find_if(s->admitted.begin(), s->admitted.end(),
+                                   [](const Item *x) { return x->nbytes < LARGE_BYTES; });
+            if (!large || hwq == 1 || it == s->admitted.end() || it == s->admitted.begin()) break;
+            Item *x = *it;
+            s->admitted.erase(it);
+            s->admitted.push_front(x);
+            continue;
+        }
         Slot *sl = nullptr;
         for (auto &x : best->slots)
             if (!x.busy) {
@@ -490,8 +511,7 @@ int progress_locked(mdt_server s)
     {
         // stored under qmu: a later submit or release adds to this value
         std::lock_guard<std::mutex> q(s->qmu);
-        s->work.store((int64_t)(s->queue.size() + s->released.size() + s->admitted.size()) + inflight,
-                      std::memory_order_release);
+        s->work.store((int64_t)(s->queue.size() + s->admitted.size()) + inflight, std::memory_order_release);
     }
     return rc;
 }
@@ -504,8 +524,9 @@ int progress(mdt_server s)
     return progress_locked(s);
 }
 
-// The progress thread runs launching rounds while anything is queued,
-// admitted or released; while launches are only in flight it reaps them at a
+// The progress thread runs launching rounds while anything is queued or
+// admitted (released requests are taken back by whichever round comes
+// next); while launches are only in flight it reaps them at a
 // slow cadence (clients testing their requests reap too); when idle it spins
 // for a while, then sleeps on a condition variable until a submit wakes it.
 void thread_main(mdt_server s)
@@ -569,13 +590,16 @@ int submit(mdt_server s, Item *it, mdt_request *req)
         s->queue.push_back(it);
         s->work.fetch_add(1, std::memory_order_release);  // under qmu: a sleeping thread sees it
     }
-    // Light load (fewer launches in flight than streams, or no progress
-    // thread): the submitter runs a progress round itself, so its request is
-    // admitted and launched now.  Under load it only queues: the progress
-    // thread cuts whatever has queued into batched launches, which keeps the
-    // cost per submit low and the launches few.
+    // While a launch slot is free and nothing else waits (or without a
+    // progress thread) the submitter runs a progress round itself, so its
+    // request is admitted and launched now.  Once the slots are full or
+    // requests queue, it only queues: the progress thread cuts whatever has
+    // queued into batched launches, which keeps the cost per submit low and
+    // the launches few.
     const bool thread = s->run_thread.load(std::memory_order_acquire);
-    if (!thread || s->launches_inflight.load(std::memory_order_relaxed) < (int)s->streams.size()) progress(s);
+    const int nl = s->launches_inflight.load(std::memory_order_relaxed);
+    const bool waiting = s->work.load(std::memory_order_acquire) > (int64_t)nl + 1;  // besides this request
+    if (!thread || (nl < (int)s->streams.size() * s->cfg.max_inflight && !waiting)) progress(s);
     s->wake.notify_one();
     *req = r;
     return MDT_SUCCESS;
@@ -784,8 +808,7 @@ MDT_API int mdt_server_request_release(mdt_server srv, mdt_request *preq)
         // the next progress round returns its arena range and budget charge
         // (the client never waits for a round in progress)
         std::lock_guard<std::mutex> q(srv->qmu);
-        srv->released.push_back(it);
-        srv->work.fetch_add(1, std::memory_order_release);
+        srv->released.push_back(it);  // taken back by the next round; no round of its own
     }
     (*preq)->magic = 0;
     delete *preq;
