@@ -45,17 +45,22 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_TABLE = os.path.join(HERE, "profiles", "hbm_traffic.md")
 
 
+# the sources that decide what the kernels execute: kernel bodies, the
+# layout program and its tables, launch selection and the batch kernels
+KERNEL_SOURCES = ("batch.hip", "compile.cpp", "core.h", "device.h", "device.hip", "layout_dev.h", "types.cpp",
+                  "xfer.h")
+
+
 def kernel_sources_sha():
-    """sha256 over the library's sources and header: a measured HBM traffic
-    figure holds only for the sources it was measured on."""
+    """sha256 over the kernel sources and the header: a measured HBM traffic
+    figure holds only for the kernels it was measured on."""
     import hashlib
 
     h = hashlib.sha256()
     src = os.path.join(HERE, "paper_2402_12274_amd", "csrc")
-    for name in sorted(os.listdir(src)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(src, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(src, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     with open(os.path.join(HERE, "include", "mdt.h"), "rb") as f:
         h.update(f.read())
     return h.hexdigest()[:16]
