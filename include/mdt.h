@@ -286,8 +286,8 @@ MDT_API int mdt_batch_add_unpack(mdt_batch b, const void *inbuf, mdt_count insiz
  * of tiles over workgroups, 1 = dynamic (atomic tile counter).  order: 1 =
  * tiles run in the order of the typed address they start at, so requests
  * that touch the same memory (faces sharing cache lines) run together; with
- * the static policy each XCD (its own L2) takes one contiguous slice of
- * that order. */
+ * the static policy the ordered tiles are dealt to the XCDs (each has its
+ * own L2) in groups of neighbours. */
 typedef struct mdt_batch_config {
     int tile_chunks;    /* 16-byte chunks per workgroup tile: 256, 512, 1024, 2048, 4096 */
     int wgs_per_cu;     /* persistent workgroups per compute unit, 1..16; 0: one workgroup per tile */

@@ -10,7 +10,7 @@
 // CUs) pulling tiles in a static strided order or from an atomic counter, or
 // one workgroup per tile.  Tiles run in request order or in the order of the
 // typed address they start at (requests that share cache lines then run
-// together, each XCD taking one slice).  Each tile finds its request by
+// together, neighbours on the same XCD).  Each tile finds its request by
 // binary search over the prefix, reads the request's layout program through
 // the scalar cache, and runs exactly the tile bodies of the single-request
 // kernels, so every byte is identical to the request run alone.  The launch
@@ -290,18 +290,21 @@ int init_device(mdt_batch_s *b)
 // XCDs of the device: workgroup b of a launch runs on XCD b mod XCDS
 // (round-robin dispatch), and each XCD has its own L2.
 constexpr int XCDS = 8;
+constexpr int64_t XCD_GROUP = 8;
 
 // Typed-address order of each direction's tiles (the address a tile's first
 // packed byte comes from or goes to).  With the static policy slot t of a
-// direction runs on XCD t mod XCDS, so the sorted tiles are dealt out as
-// XCDS contiguous slices, one per XCD, each run in address order.
+// direction runs on XCD t mod XCDS, so the sorted tiles are dealt out to the
+// XCDs in groups of XCD_GROUP neighbours: tiles that touch the same lines
+// share an L2, and every XCD still gets a spread of the whole address range
+// (contiguous slices left whole faces on one XCD).
 int build_order(mdt_batch_s *b, const ReqDesc *D, const int64_t *tile0, const BatchHeader &H)
 {
     const int64_t T = b->cfg.tile_chunks;
     const int64_t total = H.ntiles_dir[0] + H.ntiles_dir[1];
     if (total > INT32_MAX / 2) return MDT_ERR_COUNT;
-    // slots: tiles rounded up to a multiple of XCDS per direction
-    const size_t need = (size_t)(total + 2 * XCDS);
+    // slots: tiles rounded up to a multiple of XCDS * XCD_GROUP per direction
+    const size_t need = (size_t)(total + 2 * XCDS * XCD_GROUP);
     if (need > b->order_cap) {
         size_t cap = std::max<size_t>(need, 2 * b->order_cap);
         (void)hipDeviceSynchronize();  // a launch in flight may read the old table
@@ -351,10 +354,16 @@ int build_order(mdt_batch_s *b, const ReqDesc *D, const int64_t *tile0, const Ba
         const int64_t n = (int64_t)keys.size();
         int64_t nslots = n;
         if (b->cfg.policy == 0 && n > 0) {
-            const int64_t C = (n + XCDS - 1) / XCDS;
-            nslots = C * XCDS;
+            // groups g = 0, 1, ... of XCD_GROUP sorted tiles; group g runs on
+            // XCD g mod XCDS.  Slot t (XCD t mod XCDS, i-th slot of that XCD)
+            // takes position p of group (i / XCD_GROUP) * XCDS + XCD.
+            const int64_t groups = (n + XCD_GROUP - 1) / XCD_GROUP;
+            const int64_t rounds = (groups + XCDS - 1) / XCDS;
+            nslots = rounds * XCDS * XCD_GROUP;
             for (int64_t t = 0; t < nslots; t++) {
-                const int64_t p = (t % XCDS) * C + t / XCDS;
+                const int64_t x = t % XCDS, i = t / XCDS;
+                const int64_t g = (i / XCD_GROUP) * XCDS + x;
+                const int64_t p = g * XCD_GROUP + i % XCD_GROUP;
                 b->h_order[slot0 + t] = p < n ? keys[(size_t)p].second : -1;
             }
         } else {
