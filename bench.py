@@ -91,7 +91,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="halo",
-                    choices=["halo", "particles", "hindexed", "contig", "rows", "small", "serve", "batch4096"])
+                    choices=["halo", "particles", "hindexed", "contig", "rows", "small", "serve", "batch4096", "copy"])
     ap.add_argument("--duration", type=float, default=15.0, help="serve: seconds of trace per replay")
     ap.add_argument("--rate", type=float, default=20000.0, help="serve: Poisson arrival rate (requests/s)")
     ap.add_argument("--sat-rate", type=float, default=150000.0,
@@ -320,6 +320,117 @@ def serve_bench(args, torch, mdt):
     return 0
 
 
+def copy_bench(args, torch, mdt):
+    """Periodic halo self-exchange on a float64 512^3 array: for each dim and
+    ghost width 1 and 4, the interior layer next to each side is copied into
+    the ghost layer on the opposite side (12 copies per step), as typed
+    copies (one pass, no staging) and as pack + unpack through a staging
+    buffer (plain launches, and one batched launch per direction)."""
+    dev = torch.device("cuda:0")
+    n = 512
+    D = inputs.DOUBLE
+    R = max(1, args.rotate)
+    arrs = [torch.from_numpy(inputs.random_bytes(n ** 3 * 8, seed=inputs.DEFAULT_SEED + r)).to(dev) for r in range(R)]
+    pairs = []
+    for w in (1, 4):
+        for dim in (0, 1, 2):
+            for side in ("lo", "hi"):
+                src = inputs.halo_face(n, w, dim, side)
+                sub = [n - 2 * w] * 3
+                st = [w] * 3
+                sub[dim] = w
+                st[dim] = n - w if side == "lo" else 0  # ghost layer on the opposite side
+                pairs.append((mdt.build_type(src), mdt.build_type(("subarray", [n, n, n], sub, st, "C", D))))
+    sizes = [a.size() for a, _ in pairs]
+    stage = [torch.empty(s, dtype=torch.uint8, device=dev) for s in sizes]
+    stream = torch.cuda.current_stream()
+    ms = mdt.Stream(stream.cuda_stream)
+    useful = 2 * sum(sizes)  # algorithmic bytes of the exchange: each byte read once, written once
+
+    def copies(r):
+        a = arrs[r].data_ptr()
+        for (ta, tb), _ in zip(pairs, sizes):
+            mdt.mdt_typed_copy_enqueue(a, 1, ta, a, 1, tb, 0, -1, ms)
+
+    def staged(r):
+        a = arrs[r].data_ptr()
+        for (ta, _), buf in zip(pairs, stage):
+            mdt.mdt_pack_enqueue(a, 1, ta, 0, buf.data_ptr(), -1, ms)
+        for (_, tb), buf, s in zip(pairs, stage, sizes):
+            mdt.mdt_unpack_enqueue(buf.data_ptr(), s, a, 1, tb, 0, ms)
+
+    batches = []
+    for r in range(R):
+        bp, bu = mdt.Batch(), mdt.Batch()
+        for (ta, tb), buf, s in zip(pairs, stage, sizes):
+            bp.add_pack(arrs[r].data_ptr(), 1, ta, 0, buf.data_ptr(), -1)
+            bu.add_unpack(buf.data_ptr(), s, arrs[r].data_ptr(), 1, tb, 0)
+        batches.append((bp, bu))
+    batches[0][0].autotune(ms)
+    batches[0][1].autotune(ms)
+    for bp, bu in batches[1:]:
+        bp.set_config(batches[0][0].get_config())
+        bu.set_config(batches[0][1].get_config())
+
+    def batched(r):
+        bp, bu = batches[r]
+        bp.launch(ms)
+        bu.launch(ms)
+
+    def timed(fn, launches):
+        for i in range(max(args.warmup, R)):
+            fn(i % R)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for i in range(args.steps):
+            fn(i % R)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        dev_s = e0.elapsed_time(e1) * 1e-3
+        return {"GBps": round(useful * args.steps / dt / 1e9, 2), "ms_per_step": round(dt / args.steps * 1e3, 4),
+                "avg_launch_us": round(dev_s / (launches * args.steps) * 1e6, 2)}
+
+    cbatches = []
+    for r in range(R):
+        b = mdt.Batch()
+        for ta, tb in pairs:
+            b.add_copy(arrs[r].data_ptr(), 1, ta, arrs[r].data_ptr(), 1, tb, 0, -1)
+        cbatches.append(b)
+    cbatches[0].autotune(ms)
+    for b in cbatches[1:]:
+        b.set_config(cbatches[0].get_config())
+
+    def copies_batched(r):
+        cbatches[r].launch(ms)
+
+    res_copy = timed(copies, len(pairs))
+    res_copy_batched = timed(copies_batched, 1)
+    res_staged = timed(staged, 2 * len(pairs))
+    res_batched = timed(batched, 2)
+    achieved = useful / (res_copy_batched["avg_launch_us"] * 1e-6) / 1e9
+    out = {
+        "metric": METRIC, "value": res_copy_batched["GBps"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res_copy_batched["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "periodic halo self-exchange: float64 512^3 array, ghost widths 1 and 4, each "
+                               "interior layer copied into the opposite ghost layer (12 typed copies per step)",
+                   "bytes_per_step": useful, "rotating_copies": R,
+                   "autotuned": mdt.config_dict(cbatches[0].get_config())},
+        "typed_copy_batched": res_copy_batched, "typed_copy_plain": res_copy, "pack_unpack_plain": res_staged,
+        "pack_unpack_batched": res_batched,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "kernel": "batch_kernel (typed copies, one launch per step)",
+                     "avg_launch_us": res_copy_batched["avg_launch_us"], "bytes_per_launch": int(useful)},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def batch_bench(args, torch, mdt):
     """4096 pack requests (sizes log-uniform 64 B..16 MiB; vectors with stride
     2..64, halo faces, the 1M-block hindexed layout) run as one persistent
@@ -404,6 +515,8 @@ def main():
         return serve_bench(args, torch, mdt)
     if args.workload == "batch4096":
         return batch_bench(args, torch, mdt)
+    if args.workload == "copy":
+        return copy_bench(args, torch, mdt)
     W = workload(args.workload)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()

@@ -235,6 +235,20 @@ MDT_API int mdt_pack(const void *inbuf, mdt_count incount, mdt_type t, mdt_count
 MDT_API int mdt_unpack(const void *inbuf, mdt_count insize, void *outbuf, mdt_count outcount, mdt_type t,
                        mdt_count outoffset, mdt_count *actual_unpack_bytes);
 
+/* Blocking typed copy (Derived Datatypes: a typemap describes the layout on
+ * each side of a transfer; this is the transfer to oneself, as a send and a
+ * matching receive with different types): byte p of the packed stream of
+ * (srccount x srctype) at origin src goes to stream position p of
+ * (dstcount x dsttype) at origin dst, for p in [offset, offset + actual),
+ * actual = clamp(srccount*srcsize - offset, 0, max_bytes) (max_bytes = -1:
+ * unlimited), in one pass with no packed staging buffer.  Bytes of dst
+ * outside its typemap are never written.  The bytes read and the bytes
+ * written must not overlap.  Errors: MDT_ERR_TRUNCATE if actual >
+ * dstcount*dstsize - offset, MDT_ERR_OVERLAP if (dstcount x dsttype) has
+ * overlapping bytes; nothing is written on error. */
+MDT_API int mdt_typed_copy(const void *src, mdt_count srccount, mdt_type srctype, void *dst, mdt_count dstcount,
+                           mdt_type dsttype, mdt_count offset, mdt_count max_bytes, mdt_count *actual);
+
 /* ---------------------------------------------------------------------
  * Stream-ordered work (Offloading Asynchronous Operations: work enqueued
  * on a GPU stream runs after earlier work on that stream and before later
@@ -252,6 +266,10 @@ MDT_API int mdt_pack_enqueue(const void *inbuf, mdt_count incount, mdt_type t, m
 MDT_API int mdt_unpack_enqueue(const void *inbuf, mdt_count insize, void *outbuf, mdt_count outcount,
                                mdt_type t, mdt_count outoffset, mdt_count *actual_unpack_bytes,
                                mdt_stream s, mdt_request *req);
+/* As mdt_typed_copy, enqueued on stream s. */
+MDT_API int mdt_typed_copy_enqueue(const void *src, mdt_count srccount, mdt_type srctype, void *dst,
+                                   mdt_count dstcount, mdt_type dsttype, mdt_count offset, mdt_count max_bytes,
+                                   mdt_count *actual, mdt_stream s, mdt_request *req);
 /* Device flatten: write segments [iov_offset, iov_offset + max_iov_len) of
  * committed type t into the device array dev_iov, each base being
  * `base` + displacement (base may be NULL for raw displacements); enqueued
@@ -282,6 +300,11 @@ MDT_API int mdt_batch_add_pack(mdt_batch b, const void *inbuf, mdt_count incount
 MDT_API int mdt_batch_add_unpack(mdt_batch b, const void *inbuf, mdt_count insize, void *outbuf,
                                  mdt_count outcount, mdt_type t, mdt_count outoffset,
                                  mdt_count *actual_unpack_bytes);
+/* A typed copy (as mdt_typed_copy) as a request of the batch: it runs in the
+ * first launch, with the pack requests; unpack requests run after it. */
+MDT_API int mdt_batch_add_copy(mdt_batch b, const void *src, mdt_count srccount, mdt_type srctype, void *dst,
+                               mdt_count dstcount, mdt_type dsttype, mdt_count offset, mdt_count max_bytes,
+                               mdt_count *actual);
 /* Tuning knobs of the persistent launch.  policy: 0 = static strided split
  * of tiles over workgroups, 1 = dynamic (atomic tile counter).  order: 1 =
  * tiles run in the order of the typed address they start at, so requests

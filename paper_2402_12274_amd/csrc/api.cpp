@@ -146,6 +146,49 @@ int unpack_common(const void *inbuf, int64_t insize, void *outbuf, int64_t outco
     return MDT_SUCCESS;
 }
 
+int copy_common(const void *src, int64_t srccount, mdt_type srctype, void *dst, int64_t dstcount, mdt_type dsttype,
+                int64_t offset, int64_t max_bytes, int64_t *actual, hipStream_t s, mdt_request *req)
+{
+    if (!actual || offset < 0 || max_bytes < -1) return MDT_ERR_ARG;
+    Compiled *Cs, *Cd;
+    DeviceTables *Ds = nullptr, *Dd = nullptr;
+    int64_t total_s, total_d;
+    // sizes, truncation and overlap are checked before any device work
+    int rc = prepare(srctype, srccount, &Cs, nullptr, &total_s);
+    if (rc) return rc;
+    rc = prepare(dsttype, dstcount, &Cd, nullptr, &total_d);
+    if (rc) return rc;
+    int64_t n = total_s - offset;
+    if (n < 0) n = 0;
+    if (max_bytes >= 0 && n > max_bytes) n = max_bytes;
+    int64_t room = total_d - offset;
+    if (room < 0) room = 0;
+    if (n > room) return MDT_ERR_TRUNCATE;
+    rc = check_unpack_overlap(Cd, dstcount);
+    if (rc) return rc;
+    if (n > 0 && (!src || !dst)) return MDT_ERR_ARG;
+    if (n > 0) {
+        rc = device_tables(Cs, &Ds);
+        if (rc) return rc;
+        rc = device_tables(Cd, &Dd);
+        if (rc) return rc;
+        CopyArgs A{};
+        A.src = (const uint8_t *)src;
+        A.dst = (uint8_t *)dst;
+        A.off = offset;
+        A.nbytes = n;
+        A.nchunks = (n + 15) / 16;
+        A.src_elem1 = offset + n <= Ds->lay.size;
+        A.dst_elem1 = offset + n <= Dd->lay.size;
+        rc = launch_copy(Ds->lay, Dd->lay, A, s);
+        if (rc) return rc;
+    }
+    rc = request_from_stream(s, req);
+    if (rc) return rc;
+    *actual = n;
+    return MDT_SUCCESS;
+}
+
 int wait_request(mdt_request r)
 {
     if (r->kind == REQ_EVENT) {
@@ -178,6 +221,7 @@ extern "C" {
 MDT_API int mdt_pack(const void *inbuf, mdt_count incount, mdt_type t, mdt_count inoffset, void *outbuf,
                      mdt_count max_pack_bytes, mdt_count *actual_pack_bytes)
 {
+    if (!actual_pack_bytes) return MDT_ERR_ARG;
     int64_t n = 0;
     int rc = pack_common(inbuf, incount, t, inoffset, outbuf, max_pack_bytes, &n, nullptr, nullptr);
     if (rc) return rc;
@@ -190,9 +234,26 @@ MDT_API int mdt_pack(const void *inbuf, mdt_count incount, mdt_type t, mdt_count
     return MDT_SUCCESS;
 }
 
+MDT_API int mdt_typed_copy(const void *src, mdt_count srccount, mdt_type srctype, void *dst, mdt_count dstcount,
+                           mdt_type dsttype, mdt_count offset, mdt_count max_bytes, mdt_count *actual)
+{
+    if (!actual) return MDT_ERR_ARG;
+    int64_t n = 0;
+    int rc = copy_common(src, srccount, srctype, dst, dstcount, dsttype, offset, max_bytes, &n, nullptr, nullptr);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+        set_hip_error((int)e);
+        return MDT_ERR_HIP;
+    }
+    *actual = n;
+    return MDT_SUCCESS;
+}
+
 MDT_API int mdt_unpack(const void *inbuf, mdt_count insize, void *outbuf, mdt_count outcount, mdt_type t,
                        mdt_count outoffset, mdt_count *actual_unpack_bytes)
 {
+    if (!actual_unpack_bytes) return MDT_ERR_ARG;
     int64_t n = 0;
     int rc = unpack_common(inbuf, insize, outbuf, outcount, t, outoffset, &n, nullptr, nullptr);
     if (rc) return rc;
@@ -239,6 +300,14 @@ MDT_API int mdt_unpack_enqueue(const void *inbuf, mdt_count insize, void *outbuf
 {
     if (!valid_stream(s)) return MDT_ERR_ARG;
     return unpack_common(inbuf, insize, outbuf, outcount, t, outoffset, actual_unpack_bytes, s->s, req);
+}
+
+MDT_API int mdt_typed_copy_enqueue(const void *src, mdt_count srccount, mdt_type srctype, void *dst,
+                                   mdt_count dstcount, mdt_type dsttype, mdt_count offset, mdt_count max_bytes,
+                                   mdt_count *actual, mdt_stream s, mdt_request *req)
+{
+    if (!valid_stream(s)) return MDT_ERR_ARG;
+    return copy_common(src, srccount, srctype, dst, dstcount, dsttype, offset, max_bytes, actual, s->s, req);
 }
 
 MDT_API int mdt_type_iov_enqueue(mdt_type t, mdt_count iov_offset, mdt_iov *dev_iov, mdt_count max_iov_len,

@@ -26,172 +26,19 @@
 
 #include "core.h"
 #include "device.h"
+#include "batch_kernel.h"
 #include "requests.h"
-#include "xfer.h"
 
-namespace mdt {
-
-struct ReqDesc {
-    uint64_t lay;          // address of the device copy of the request's layout program
-    const uint8_t *typed;
-    uint8_t *packed;
-    int64_t off, nbytes, head, nchunks;
-    int32_t unpack, kind;
-    int32_t elem1, body;  // BODY_DENSE, BODY_RUNS or BODY_CHUNK
-};
-
-// Tile bodies a batch kernel carries (a bit set): a kernel compiled for one
-// body needs only that body's registers, so a direction whose requests all
-// take one path runs at that path's occupancy.
-constexpr int BODY_DENSE = 1;  // record view, LDS-staged
-constexpr int BODY_RUNS = 2;   // run tables, LDS-cached group slice
-constexpr int BODY_CHUNK = 4;  // chunk path
-constexpr int BODY_ALL = 7;
-
-// Descriptors are stored pack requests first, so each direction's tiles
-// form one range: [0, ntiles_dir[0]) for pack, then unpack.
-struct BatchHeader {
-    int64_t nreq_dir[2];    // requests per direction
-    int64_t ntiles_dir[2];  // tiles per direction
-    int64_t tile_chunks;
-    int64_t ordered;        // 1: slots map to tiles through the order table
-    int64_t nslots_dir[2];  // order-table slots per direction (>= tiles; -1 entries are empty)
-};
-
-// Chunks [c0, cend) of one request, with the single-request bodies.
-template <int UNPACK, int BODY>
-__device__ __forceinline__ void run_tile(const DevLayout &L, const XferArgs &A, int body, int kind, int64_t c0,
-                                         int64_t cend, uint8_t *lds_dyn)
-{
-    if ((BODY & BODY_DENSE) && body == BODY_DENSE) {
-        // sub-tiles sized to the type's LDS budget; LDS is reused between them
-        const int64_t st = L.rec.tile_chunks;
-        for (int64_t s0 = c0; s0 < cend; s0 += st) {
-            int64_t s1 = s0 + st < cend ? s0 + st : cend;
-            if (UNPACK) dense_unpack_tile(L, A, s0, s1, lds_dyn);
-            else dense_pack_tile(L, A, s0, s1, lds_dyn);
-            __syncthreads();
-        }
-        return;
-    }
-    if ((BODY & BODY_RUNS) && body == BODY_RUNS) {
-        RunsCache &C = *reinterpret_cast<RunsCache *>(lds_dyn);
-        for (int64_t s0 = c0; s0 < cend; s0 += 1024) {
-            int64_t s1 = s0 + 1024 < cend ? s0 + 1024 : cend;
-            runs_tile<UNPACK != 0>(L, A, s0, s1, C);
-            __syncthreads();  // the cache is refilled for the next sub-tile
-        }
-        return;
-    }
-    if (BODY & BODY_CHUNK) {
-        for (int64_t s0 = c0; s0 < cend; s0 += 1024) {
-            int64_t s1 = s0 + 1024 < cend ? s0 + 1024 : cend;
-            if (UNPACK) {
-                if (kind == KIND_CONTIG) unpack_tile4<KIND_CONTIG>(L, A, s0, s1);
-                else if (kind == KIND_SINGLE) unpack_tile4<KIND_SINGLE>(L, A, s0, s1);
-                else unpack_tile4<KIND_MULTI>(L, A, s0, s1);
-            } else {
-                if (kind == KIND_CONTIG) pack_tile4<KIND_CONTIG>(L, A, s0, s1);
-                else if (kind == KIND_SINGLE) pack_tile4<KIND_SINGLE>(L, A, s0, s1);
-                else pack_tile4<KIND_MULTI>(L, A, s0, s1);
-            }
-        }
-    }
-}
-
-__global__ void batch_counter_reset(unsigned long long *counter) { *counter = 0ull; }
-
-// The same value in every lane, as a scalar (the tile index a workgroup
-// works on is uniform; saying so keeps the request lookup and the layout
-// reads on the scalar unit).
-__device__ __forceinline__ int64_t uniform64(int64_t v)
-{
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-// A layout program read through the constant address space: it does not
-// change while a kernel runs, so uniform reads of it become scalar loads, as
-// they are for a layout passed by value as a kernel argument.
-__device__ __forceinline__ const DevLayout &const_layout(uint64_t addr)
-{
-    return *(const DevLayout *)(const __attribute__((address_space(4))) DevLayout *)(uintptr_t)addr;
-}
-
-// Batch kernel for one direction.  POLICY 0: tile t = blockIdx.x + k *
-// gridDim.x (with one workgroup per tile, each workgroup takes one tile);
-// POLICY 1: tiles taken from an atomic counter.  Every workgroup leaves the
-// loop once the tile index passes the direction's last tile.
-template <int POLICY, int UNPACK, int BODY>
-__global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restrict__ H,
-                                                    const ReqDesc *__restrict__ R,
-                                                    const int64_t *__restrict__ tile0,
-                                                    const int32_t *__restrict__ order,
-                                                    unsigned long long *counter)
-{
-    extern __shared__ __align__(16) uint8_t lds_dyn[];
-    __shared__ int64_t s_t;
-    const int64_t T = H->tile_chunks;
-    const bool ordered = H->ordered != 0;
-    // this direction's requests [r0, r1) and index range [t_begin, t_end):
-    // tiles, or slots of the order table
-    const int64_t r0 = UNPACK ? H->nreq_dir[0] : 0, r1 = r0 + H->nreq_dir[UNPACK];
-    const int64_t t_begin = ordered ? (UNPACK ? H->nslots_dir[0] : 0) : (UNPACK ? H->ntiles_dir[0] : 0);
-    const int64_t t_end = t_begin + (ordered ? H->nslots_dir[UNPACK] : H->ntiles_dir[UNPACK]);
-    int64_t t;
-    if (POLICY == 0) {
-        t = t_begin + blockIdx.x;
-    } else {
-        if (threadIdx.x == 0) s_t = t_begin + (int64_t)atomicAdd(counter, 1ull);
-        __syncthreads();
-        t = uniform64(s_t);
-    }
-    while (t < t_end) {
-        const int64_t tile = ordered ? (int64_t)order[t] : t;  // -1: an empty slot
-        if (tile >= 0) {
-            // request holding the tile: last r with tile0[r] <= tile
-            int64_t lo = r0, hi = r1 - 1;
-            while (lo < hi) {
-                int64_t mid = (lo + hi + 1) >> 1;
-                if (tile0[mid] <= tile) lo = mid; else hi = mid - 1;
-            }
-            const ReqDesc &D = R[lo];
-            const DevLayout &L = const_layout(D.lay);
-            XferArgs A;
-            A.typed = D.typed;
-            A.packed = D.packed;
-            A.off = D.off;
-            A.nbytes = D.nbytes;
-            A.head = D.head;
-            A.nchunks = D.nchunks;
-            A.tile_chunks = T;
-            A.elem1 = D.elem1;
-            int64_t c0 = (tile - tile0[lo]) * T;
-            int64_t cend = c0 + T < D.nchunks ? c0 + T : D.nchunks;
-            run_tile<UNPACK, BODY>(L, A, D.body, D.kind, c0, cend, lds_dyn);
-        }
-        if (POLICY == 0) {
-            t += gridDim.x;
-        } else {
-            __syncthreads();
-            if (threadIdx.x == 0) s_t = t_begin + (int64_t)atomicAdd(counter, 1ull);
-            __syncthreads();
-            t = uniform64(s_t);
-        }
-    }
-}
-
-}  // namespace mdt
 
 using namespace mdt;
 
 constexpr uint32_t BATCH_MAGIC = 0x6d647442u;
 
 struct BatchReq {
-    TypeNode *type;  // retained
+    TypeNode *type;   // retained
     ReqDesc d;
-    int32_t lds;     // dynamic LDS the request's body needs
+    int32_t lds;      // dynamic LDS the request's body needs
+    TypeNode *type2;  // copy: the destination type (retained), else NULL
 };
 
 struct mdt_batch_s {
@@ -226,6 +73,10 @@ struct mdt_batch_s {
     uint8_t *graph_buf = nullptr;
     int32_t *graph_order = nullptr;
 };
+
+namespace mdt {
+__global__ void batch_counter_reset(unsigned long long *counter) { *counter = 0ull; }
+}  // namespace mdt
 
 namespace {
 
@@ -447,23 +298,13 @@ int grid_of(const mdt_batch_s *b, int dir)
     return (int)std::min<int64_t>(std::max<int64_t>(1, g), INT32_MAX);
 }
 
-template <int POLICY, int UNPACK, int BODY>
-void launch_one(mdt_batch_s *b, hipStream_t s, dim3 grid, size_t lds, unsigned long long *ctr)
+template <int POLICY, int UNPACK>
+void launch_dir(mdt_batch_s *b, hipStream_t s, dim3 grid, size_t lds, unsigned long long *ctr, int body)
 {
     const BatchHeader *H = (const BatchHeader *)b->d_buf;
     const ReqDesc *R = (const ReqDesc *)(b->d_buf + desc_off());
     const int64_t *tile0 = (const int64_t *)(b->d_buf + tile_off(b->cap));
-    hipLaunchKernelGGL((batch_kernel<POLICY, UNPACK, BODY>), grid, dim3(256), lds, s, H, R, tile0, b->d_order, ctr);
-}
-
-template <int POLICY, int UNPACK>
-void launch_dir(mdt_batch_s *b, hipStream_t s, dim3 grid, size_t lds, unsigned long long *ctr, int body)
-{
-    // a kernel with only the body the direction needs, else one with all
-    if (body == BODY_DENSE) launch_one<POLICY, UNPACK, BODY_DENSE>(b, s, grid, lds, ctr);
-    else if (body == BODY_RUNS) launch_one<POLICY, UNPACK, BODY_RUNS>(b, s, grid, lds, ctr);
-    else if (body == BODY_CHUNK) launch_one<POLICY, UNPACK, BODY_CHUNK>(b, s, grid, lds, ctr);
-    else launch_one<POLICY, UNPACK, BODY_ALL>(b, s, grid, lds, ctr);
+    launch_batch_dir<POLICY, UNPACK>(grid, lds, s, H, R, tile0, b->d_order, ctr, body);
 }
 
 void enqueue_kernels(mdt_batch_s *b, hipStream_t s)
@@ -567,13 +408,15 @@ int body_of(const DevLayout &L, const XferArgs &A, bool unpack, int32_t *lds)
     return BODY_CHUNK;
 }
 
-int add_req(mdt_batch b, TypeNode *t, const ReqDesc &d, int32_t lds)
+int add_req(mdt_batch b, TypeNode *t, const ReqDesc &d, int32_t lds, TypeNode *t2 = nullptr)
 {
     try {
         retain(t);
-        b->reqs.push_back({t, d, lds});
+        if (t2) retain(t2);
+        b->reqs.push_back({t, d, lds, t2});
     } catch (...) {
         release(t);
+        if (t2) release(t2);
         return MDT_ERR_NO_MEM;
     }
     b->dirty = true;
@@ -601,7 +444,10 @@ MDT_API int mdt_batch_create(mdt_batch *out)
 MDT_API int mdt_batch_clear(mdt_batch b)
 {
     if (!valid_batch(b)) return MDT_ERR_ARG;
-    for (auto &r : b->reqs) release(r.type);
+    for (auto &r : b->reqs) {
+        release(r.type);
+        if (r.type2) release(r.type2);
+    }
     b->reqs.clear();
     b->dirty = true;
     return MDT_SUCCESS;
@@ -675,6 +521,51 @@ MDT_API int mdt_batch_add_unpack(mdt_batch b, const void *inbuf, mdt_count insiz
         if (rc) return rc;
     }
     *actual_unpack_bytes = insize;
+    return MDT_SUCCESS;
+}
+
+MDT_API int mdt_batch_add_copy(mdt_batch b, const void *src, mdt_count srccount, mdt_type srctype, void *dst,
+                               mdt_count dstcount, mdt_type dsttype, mdt_count offset, mdt_count max_bytes,
+                               mdt_count *actual)
+{
+    if (!valid_batch(b) || !actual || offset < 0 || max_bytes < -1) return MDT_ERR_ARG;
+    Compiled *Cs, *Cd;
+    DeviceTables *Ds = nullptr, *Dd = nullptr;
+    int64_t total_s, total_d;
+    int rc = prepare(srctype, srccount, &Cs, nullptr, &total_s);
+    if (rc) return rc;
+    rc = prepare(dsttype, dstcount, &Cd, nullptr, &total_d);
+    if (rc) return rc;
+    int64_t n = std::max<int64_t>(0, total_s - offset);
+    if (max_bytes >= 0) n = std::min<int64_t>(n, max_bytes);
+    if (n > std::max<int64_t>(0, total_d - offset)) return MDT_ERR_TRUNCATE;
+    rc = check_unpack_overlap(Cd, dstcount);
+    if (rc) return rc;
+    if (n > 0 && (!src || !dst)) return MDT_ERR_ARG;
+    if (n > 0) {
+        rc = device_tables(Cs, &Ds);
+        if (rc) return rc;
+        rc = device_tables(Cd, &Dd);
+        if (rc) return rc;
+        ReqDesc d{};
+        d.lay = (uint64_t)(uintptr_t)Ds->d_lay;
+        d.typed = (const uint8_t *)src;
+        d.packed = (uint8_t *)dst;
+        d.off = offset;
+        d.nbytes = n;
+        d.head = 0;
+        d.nchunks = (n + 15) / 16;
+        d.unpack = 0;
+        d.kind = Ds->lay.kind;
+        d.elem1 = offset + n <= Ds->lay.size;
+        d.body = BODY_COPY;
+        d.lay2 = (uint64_t)(uintptr_t)Dd->d_lay;
+        d.kind2 = Dd->lay.kind;
+        d.elem1_2 = offset + n <= Dd->lay.size;
+        rc = add_req(b, reinterpret_cast<TypeNode *>(srctype), d, 0, reinterpret_cast<TypeNode *>(dsttype));
+        if (rc) return rc;
+    }
+    *actual = n;
     return MDT_SUCCESS;
 }
 

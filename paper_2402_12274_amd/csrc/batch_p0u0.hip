@@ -1,0 +1,13 @@
+// batch_p0u0.hip -- batch kernel variants for the static split, pack (and copy) direction.
+#include "batch_kernel.h"
+
+namespace mdt {
+
+template <>
+void launch_batch_dir<0, 0>(dim3 grid, size_t lds, hipStream_t s, const BatchHeader *H, const ReqDesc *R,
+                            const int64_t *tile0, const int32_t *order, unsigned long long *counter, int body)
+{
+    launch_batch_dir_impl<0, 0>(grid, lds, s, H, R, tile0, order, counter, body);
+}
+
+}  // namespace mdt

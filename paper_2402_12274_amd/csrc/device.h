@@ -20,7 +20,21 @@ struct XferArgs {
     int32_t pad_;
 };
 
+// One typed copy: bytes [off, off + nbytes) of the source stream go to the
+// same positions of the destination stream.  Chunk c covers stream bytes
+// [off + 16c, off + 16c + 16).
+struct CopyArgs {
+    const uint8_t *src;    // origin of the source buffer
+    uint8_t *dst;          // origin of the destination buffer
+    int64_t off;           // first stream position copied
+    int64_t nbytes;        // bytes copied
+    int64_t nchunks;       // ceil(nbytes / 16)
+    int32_t src_elem1;     // off + nbytes <= source element size
+    int32_t dst_elem1;     // off + nbytes <= destination element size
+};
+
 XferArgs make_args(const void *typed, void *packed, int64_t off, int64_t nbytes);
+int launch_copy(const DevLayout &Ls, const DevLayout &Ld, const CopyArgs &A, hipStream_t s);
 int launch_xfer(const DevLayout &L, const XferArgs &A, bool unpack, hipStream_t s);
 int launch_flatten(Compiled *c, DeviceTables *d, int64_t off, int64_t m, mdt_iov *out, const void *base,
                    hipStream_t s);

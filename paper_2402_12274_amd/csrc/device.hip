@@ -172,6 +172,18 @@ __global__ __launch_bounds__(256) void xfer_kernel(const DevLayout L, const Xfer
     }
 }
 
+// typed copy: one tile of 1024 chunks per workgroup (four per lane)
+template <int KS, int KD>
+__global__ __launch_bounds__(256) void copy_kernel(const DevLayout Ls, const DevLayout Ld, const CopyArgs A)
+{
+    const int64_t ntiles = (A.nchunks + 1023) / 1024;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t c0 = t * 1024;
+        const int64_t cend = c0 + 1024 < A.nchunks ? c0 + 1024 : A.nchunks;
+        copy_tile4<KS, KD>(Ls, Ld, A, c0, cend);
+    }
+}
+
 // dense record streams: one tile of chunks per workgroup, staged in LDS
 template <bool UNPACK>
 __global__ __launch_bounds__(256) void dense_kernel(const DevLayout L, const XferArgs A)
@@ -320,6 +332,25 @@ int launch_xfer(const DevLayout &L, const XferArgs &A0, bool unpack, hipStream_t
     default: LAUNCH(KIND_MULTI); break;
     }
 #undef LAUNCH
+    HIPCHK(hipGetLastError());
+    return MDT_SUCCESS;
+}
+
+template <int KS>
+static void launch_copy_kd(const DevLayout &Ls, const DevLayout &Ld, const CopyArgs &A, dim3 g, hipStream_t s)
+{
+    if (Ld.kind == KIND_CONTIG) hipLaunchKernelGGL((copy_kernel<KS, KIND_CONTIG>), g, dim3(256), 0, s, Ls, Ld, A);
+    else if (Ld.kind == KIND_SINGLE) hipLaunchKernelGGL((copy_kernel<KS, KIND_SINGLE>), g, dim3(256), 0, s, Ls, Ld, A);
+    else hipLaunchKernelGGL((copy_kernel<KS, KIND_MULTI>), g, dim3(256), 0, s, Ls, Ld, A);
+}
+
+int launch_copy(const DevLayout &Ls, const DevLayout &Ld, const CopyArgs &A, hipStream_t s)
+{
+    if (A.nbytes == 0 || Ls.kind == KIND_EMPTY || Ld.kind == KIND_EMPTY) return MDT_SUCCESS;
+    const dim3 g((unsigned)launch_grid((A.nchunks + 1023) / 1024));
+    if (Ls.kind == KIND_CONTIG) launch_copy_kd<KIND_CONTIG>(Ls, Ld, A, g, s);
+    else if (Ls.kind == KIND_SINGLE) launch_copy_kd<KIND_SINGLE>(Ls, Ld, A, g, s);
+    else launch_copy_kd<KIND_MULTI>(Ls, Ld, A, g, s);
     HIPCHK(hipGetLastError());
     return MDT_SUCCESS;
 }

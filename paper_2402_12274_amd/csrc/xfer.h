@@ -414,6 +414,73 @@ __device__ __forceinline__ void unpack_tile4(const DevLayout &L, const XferArgs 
 
 
 
+// ---------------------------------------------------------------------------
+// typed copy: a chunk of the stream gathered from one layout and scattered
+// to another, with no packed buffer in between
+
+// Stream bytes [p, p + n) (n <= 16) of layout L at origin base, as chunk
+// bytes [0, n).
+template <int KIND>
+__device__ __forceinline__ V4 gather_stream(const DevLayout &L, const uint8_t *base, uint64_t p, int n, bool elem1)
+{
+    Loc l = locate<KIND>(L, p, elem1);
+    if (n == 16 && l.rem >= 16) return load16(base + l.addr);
+    V4 acc = {0u, 0u, 0u, 0u};
+    int k = 0;
+    for (;;) {
+        int take = l.rem < n ? (int)l.rem : n;
+        if (take <= 0) break;  // unreachable for a well-formed layout; never spin
+        gather_part(acc, k, base + l.addr, take);
+        p += take;
+        k += take;
+        n -= take;
+        if (n <= 0) break;
+        l = locate<KIND>(L, p, elem1);
+    }
+    return acc;
+}
+
+// Chunk bytes [0, n) to stream bytes [p, p + n) of layout L at origin base.
+template <int KIND>
+__device__ __forceinline__ void scatter_stream(const DevLayout &L, uint8_t *base, uint64_t p, int n, const V4 &acc,
+                                               bool elem1)
+{
+    Loc l = locate<KIND>(L, p, elem1);
+    int k = 0;
+    for (;;) {
+        int take = l.rem < n ? (int)l.rem : n;
+        if (take <= 0) break;  // unreachable for a well-formed layout; never spin
+        scatter(acc, k, base + l.addr, take);
+        p += take;
+        k += take;
+        n -= take;
+        if (n <= 0) break;
+        l = locate<KIND>(L, p, elem1);
+    }
+}
+
+// A lane's chunks c0 + lane + 256u (u < 4) of a copy tile: all four are
+// gathered before any is scattered, so their loads are in flight together.
+template <int KS, int KD>
+__device__ __forceinline__ void copy_tile4(const DevLayout &Ls, const DevLayout &Ld, const CopyArgs &A, int64_t c0,
+                                           int64_t cend)
+{
+    V4 acc0 = {0u, 0u, 0u, 0u}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
+    const int64_t c = c0 + threadIdx.x;
+#define MDT_COPY_N(u) (int)min((int64_t)16, A.nbytes - 16 * (c + 256 * (u)))
+#define MDT_COPY_P(u) (uint64_t)(A.off + 16 * (c + 256 * (u)))
+    if (c < cend) acc0 = gather_stream<KS>(Ls, A.src, MDT_COPY_P(0), MDT_COPY_N(0), A.src_elem1);
+    if (c + 256 < cend) acc1 = gather_stream<KS>(Ls, A.src, MDT_COPY_P(1), MDT_COPY_N(1), A.src_elem1);
+    if (c + 512 < cend) acc2 = gather_stream<KS>(Ls, A.src, MDT_COPY_P(2), MDT_COPY_N(2), A.src_elem1);
+    if (c + 768 < cend) acc3 = gather_stream<KS>(Ls, A.src, MDT_COPY_P(3), MDT_COPY_N(3), A.src_elem1);
+    if (c < cend) scatter_stream<KD>(Ld, A.dst, MDT_COPY_P(0), MDT_COPY_N(0), acc0, A.dst_elem1);
+    if (c + 256 < cend) scatter_stream<KD>(Ld, A.dst, MDT_COPY_P(1), MDT_COPY_N(1), acc1, A.dst_elem1);
+    if (c + 512 < cend) scatter_stream<KD>(Ld, A.dst, MDT_COPY_P(2), MDT_COPY_N(2), acc2, A.dst_elem1);
+    if (c + 768 < cend) scatter_stream<KD>(Ld, A.dst, MDT_COPY_P(3), MDT_COPY_N(3), acc3, A.dst_elem1);
+#undef MDT_COPY_N
+#undef MDT_COPY_P
+}
+
 }  // namespace mdt
 
 namespace mdt {

@@ -99,6 +99,8 @@ _SIGS = {
     "mdt_type_iov": ([_P, _I64, C.POINTER(Iov), _I64, _I64P], _INT),
     "mdt_pack": ([_P, _I64, _P, _I64, _P, _I64, _I64P], _INT),
     "mdt_unpack": ([_P, _I64, _P, _I64, _P, _I64, _I64P], _INT),
+    "mdt_typed_copy": ([_P, _I64, _P, _P, _I64, _P, _I64, _I64, _I64P], _INT),
+    "mdt_typed_copy_enqueue": ([_P, _I64, _P, _P, _I64, _P, _I64, _I64, _I64P, _P, C.POINTER(_P)], _INT),
     "mdt_stream_create": ([_P, C.POINTER(_P)], _INT),
     "mdt_stream_free": ([C.POINTER(_P)], _INT),
     "mdt_pack_enqueue": ([_P, _I64, _P, _I64, _P, _I64, _I64P, _P, C.POINTER(_P)], _INT),
@@ -112,6 +114,7 @@ _SIGS = {
     "mdt_batch_clear": ([_P], _INT),
     "mdt_batch_add_pack": ([_P, _P, _I64, _P, _I64, _P, _I64, _I64P], _INT),
     "mdt_batch_add_unpack": ([_P, _P, _I64, _P, _I64, _P, _I64, _I64P], _INT),
+    "mdt_batch_add_copy": ([_P, _P, _I64, _P, _P, _I64, _P, _I64, _I64, _I64P], _INT),
     "mdt_batch_set_config": ([_P, C.POINTER(BatchConfig)], _INT),
     "mdt_batch_get_config": ([_P, C.POINTER(BatchConfig)], _INT),
     "mdt_batch_autotune": ([_P, _P, C.POINTER(BatchConfig)], _INT),
@@ -320,6 +323,16 @@ def mdt_unpack(inbuf: int, insize: int, outbuf: int, outcount: int, t: Type, out
     return n.value
 
 
+def mdt_typed_copy(src: int, srccount: int, srctype: Type, dst: int, dstcount: int, dsttype: Type, offset: int = 0,
+                   max_bytes: int = -1) -> int:
+    """Stream bytes [offset, offset + n) of (srccount x srctype) at src to the
+    same positions of (dstcount x dsttype) at dst, in one pass."""
+    n = C.c_int64()
+    check(_lib.mdt_typed_copy(_P(src), srccount, srctype.h, _P(dst), dstcount, dsttype.h, offset, max_bytes,
+                              C.byref(n)), "mdt_typed_copy")
+    return n.value
+
+
 class Stream:
     """mdt_stream wrapping a HIP stream handle (int; 0 = null stream)."""
 
@@ -358,6 +371,16 @@ def mdt_pack_enqueue(inbuf: int, incount: int, t: Type, inoffset: int, outbuf: i
     req = Request() if want_request else None
     check(_lib.mdt_pack_enqueue(_P(inbuf), incount, t.h, inoffset, _P(outbuf), max_pack_bytes, C.byref(n), stream.h,
                                 C.byref(req.handle) if req else None), "mdt_pack_enqueue")
+    return n.value, req
+
+
+def mdt_typed_copy_enqueue(src: int, srccount: int, srctype: Type, dst: int, dstcount: int, dsttype: Type,
+                           offset: int, max_bytes: int, stream: Stream, want_request: bool = False):
+    n = C.c_int64()
+    req = Request() if want_request else None
+    check(_lib.mdt_typed_copy_enqueue(_P(src), srccount, srctype.h, _P(dst), dstcount, dsttype.h, offset, max_bytes,
+                                      C.byref(n), stream.h, C.byref(req.handle) if req else None),
+          "mdt_typed_copy_enqueue")
     return n.value, req
 
 
@@ -414,6 +437,14 @@ class Batch:
         check(_lib.mdt_batch_add_unpack(self.handle, _P(inbuf), insize, _P(outbuf), outcount, t.h, outoffset,
                                         C.byref(n)), "batch_add_unpack")
         self._keep.append(t)
+        return n.value
+
+    def add_copy(self, src: int, srccount: int, srctype: Type, dst: int, dstcount: int, dsttype: Type,
+                 offset: int = 0, max_bytes: int = -1) -> int:
+        n = C.c_int64()
+        check(_lib.mdt_batch_add_copy(self.handle, _P(src), srccount, srctype.h, _P(dst), dstcount, dsttype.h,
+                                      offset, max_bytes, C.byref(n)), "batch_add_copy")
+        self._keep.extend((srctype, dsttype))
         return n.value
 
     def set_config(self, cfg: BatchConfig):
