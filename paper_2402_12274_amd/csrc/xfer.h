@@ -128,6 +128,10 @@ __device__ __forceinline__ void scatter(const V4 &acc, int k, uint8_t *d, int n)
             return;
         }
     }
+    if (n == 8 && (u & 7) == 0) {
+        *gptr((u32x2 *)d) = u32x2{dword_at(acc, k), dword_at(acc, k + 4)};
+        return;
+    }
     int h = (int)((4 - (u & 3)) & 3);
     if (h > n) h = n;
     MDT_G uint8_t *g = gptr(d);
@@ -369,6 +373,8 @@ __device__ __forceinline__ void pack_tile4(const DevLayout &L, const XferArgs &A
     }
 }
 
+// Load chunk c's packed 16 bytes and locate its first byte; false for a
+// chunk outside the tile or one that the transfer's range clips.
 template <int KIND>
 __device__ __forceinline__ bool unpack_first(const DevLayout &L, const XferArgs &A, int64_t c, int64_t cend, V4 &acc,
                                              Loc &loc)
@@ -378,11 +384,37 @@ __device__ __forceinline__ bool unpack_first(const DevLayout &L, const XferArgs 
         u32x4 v = __builtin_nontemporal_load(gptr((const u32x4 *)(A.packed - A.head + 16 * c)));
         acc = V4{v.x, v.y, v.z, v.w};
         loc = locate<KIND>(L, (uint64_t)(A.off + lo), A.elem1);
-        return loc.rem >= 16;
+        return true;
     }
     return false;
 }
 
+// Store a whole chunk (stream bytes [p, p + 16), first run l) to the typed
+// side, run by run.  Stores do not wait, so a lane's chunks overlap.
+template <int KIND>
+__device__ __forceinline__ void scatter_chunk(const DevLayout &L, const XferArgs &A, uint64_t p, Loc l, const V4 &acc)
+{
+    uint8_t *dst = const_cast<uint8_t *>(A.typed);
+    if (l.rem >= 16) {
+        scatter(acc, 0, dst + l.addr, 16);
+        return;
+    }
+    int k = 0;
+    for (;;) {
+        int take = l.rem < 16 - k ? (int)l.rem : 16 - k;
+        if (take <= 0) break;  // unreachable for a well-formed layout; never spin
+        scatter(acc, k, dst + l.addr, take);
+        k += take;
+        if (k >= 16) break;
+        l = locate<KIND>(L, p + (uint64_t)k, A.elem1);
+    }
+}
+
+// A lane's chunks c0 + lane + 256k (k < 4) of a tile: all four packed loads
+// are issued first, then each whole chunk is scattered from its loaded value
+// (stores only, so nothing waits between chunks).  Chunks clipped by the
+// transfer's range take the general body.  A tile that lies inside one run
+// is a plain copy.
 template <int KIND>
 __device__ __forceinline__ void unpack_tile4(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t cend)
 {
@@ -394,21 +426,21 @@ __device__ __forceinline__ void unpack_tile4(const DevLayout &L, const XferArgs 
         }
     }
     const int64_t c = c0 + threadIdx.x;
-    uint8_t *dst = const_cast<uint8_t *>(A.typed);
     V4 a0 = {0u, 0u, 0u, 0u}, a1 = a0, a2 = a0, a3 = a0;
     Loc l0 = {0, 0}, l1 = l0, l2 = l0, l3 = l0;
-    uint32_t fast = (uint32_t)unpack_first<KIND>(L, A, c, cend, a0, l0) |
-                    (uint32_t)unpack_first<KIND>(L, A, c + 256, cend, a1, l1) << 1 |
-                    (uint32_t)unpack_first<KIND>(L, A, c + 512, cend, a2, l2) << 2 |
-                    (uint32_t)unpack_first<KIND>(L, A, c + 768, cend, a3, l3) << 3;
-    if (fast & 1u) scatter(a0, 0, dst + l0.addr, 16);
-    if (fast & 2u) scatter(a1, 0, dst + l1.addr, 16);
-    if (fast & 4u) scatter(a2, 0, dst + l2.addr, 16);
-    if (fast & 8u) scatter(a3, 0, dst + l3.addr, 16);
+    uint32_t whole = (uint32_t)unpack_first<KIND>(L, A, c, cend, a0, l0) |
+                     (uint32_t)unpack_first<KIND>(L, A, c + 256, cend, a1, l1) << 1 |
+                     (uint32_t)unpack_first<KIND>(L, A, c + 512, cend, a2, l2) << 2 |
+                     (uint32_t)unpack_first<KIND>(L, A, c + 768, cend, a3, l3) << 3;
+    const uint64_t p = (uint64_t)(A.off + 16 * c - A.head);
+    if (whole & 1u) scatter_chunk<KIND>(L, A, p, l0, a0);
+    if (whole & 2u) scatter_chunk<KIND>(L, A, p + 4096, l1, a1);
+    if (whole & 4u) scatter_chunk<KIND>(L, A, p + 8192, l2, a2);
+    if (whole & 8u) scatter_chunk<KIND>(L, A, p + 12288, l3, a3);
 #pragma unroll 1
     for (int k = 0; k < 4; k++) {
         int64_t ck = c + 256 * k;
-        if (ck < cend && !((fast >> k) & 1u)) unpack_chunk<KIND>(L, A, ck);
+        if (ck < cend && !((whole >> k) & 1u)) unpack_chunk<KIND>(L, A, ck);
     }
 }
 
@@ -834,6 +866,76 @@ __device__ __forceinline__ int runs_find(const RunsCache &C, int n, uint64_t q)
     return lo;
 }
 
+// Chunk c of the tile lies whole inside the transfer's range.
+__device__ __forceinline__ bool runs_whole(const XferArgs &A, int64_t c, int64_t cend)
+{
+    const int64_t lo = 16 * c - A.head;
+    return c < cend && lo >= 0 && lo + 16 <= A.nbytes;
+}
+
+// Unpack: scatter a whole chunk, already loaded, run by run.
+__device__ __forceinline__ void runs_scatter(const XferArgs &A, const RunsCache &C, int n, uint64_t ebase,
+                                             int64_t eaddr, int64_t c, const V4 &acc)
+{
+    uint64_t q = (uint64_t)(A.off + 16 * c - A.head) - ebase;
+    int i = runs_find(C, n, q);
+    uint8_t *typed = const_cast<uint8_t *>(A.typed);
+    int k = 0;
+    while (k < 16 && i < n) {
+        const int64_t rem = C.pre[i + 1] - (int64_t)q;
+        const int take = rem < 16 - k ? (int)rem : 16 - k;
+        if (take > 0) scatter(acc, k, typed + eaddr + C.disp[i] + ((int64_t)q - C.pre[i]), take);
+        q += take;
+        k += take;
+        i++;
+    }
+}
+
+// Any chunk of the tile (clipped by the transfer's range, or spread over
+// more runs than the fast paths take), one run at a time.
+template <bool UNPACK>
+__device__ __forceinline__ void runs_chunk(const XferArgs &A, const RunsCache &C, int n, uint64_t ebase, int64_t eaddr,
+                                           int64_t c)
+{
+    const uint8_t *typed = A.typed;
+    const int64_t lo = 16 * c - A.head;
+    const int64_t a = lo > 0 ? lo : 0;
+    const int64_t b = lo + 16 < A.nbytes ? lo + 16 : A.nbytes;
+    int k = (int)(a - lo), m = (int)(b - a);
+    uint64_t q = (uint64_t)(A.off + a) - ebase;
+    int i = runs_find(C, n, q);
+    V4 acc = {0u, 0u, 0u, 0u};
+    if (UNPACK) {
+        u32x4 v = __builtin_nontemporal_load(gptr((const u32x4 *)(A.packed - A.head + 16 * c)));
+        acc = V4{v.x, v.y, v.z, v.w};
+    }
+    while (m > 0 && i < n) {
+        int64_t in = (int64_t)q - C.pre[i];
+        int64_t rem = C.pre[i + 1] - (int64_t)q;
+        int take = rem < m ? (int)rem : m;
+        const int64_t addr = eaddr + C.disp[i] + in;
+        if (UNPACK) {
+            scatter(acc, k, const_cast<uint8_t *>(typed) + addr, take);
+        } else {
+            if (take == 16) acc = load16(typed + addr);
+            else gather_part(acc, k, typed + addr, take);
+        }
+        q += take;
+        k += take;
+        m -= take;
+        i++;
+    }
+    if (!UNPACK) {
+        uint8_t *dst = A.packed - A.head + 16 * c;
+        if (a == lo && b == lo + 16) {
+            u32x4 v = {acc.w0, acc.w1, acc.w2, acc.w3};
+            __builtin_nontemporal_store(v, gptr((u32x4 *)dst));
+        } else {
+            for (int j = (int)(a - lo); j < (int)(b - lo); j++) gptr(dst)[j] = (uint8_t)byte_at(acc, j);
+        }
+    }
+}
+
 template <bool UNPACK>
 __device__ __forceinline__ void runs_tile(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t c1, RunsCache &C)
 {
@@ -851,43 +953,48 @@ __device__ __forceinline__ void runs_tile(const DevLayout &L, const XferArgs &A,
         }
         return;
     }
-    const uint8_t *typed = A.typed;
-    for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
-        const int64_t lo = 16 * c - A.head;
-        const int64_t a = lo > 0 ? lo : 0;
-        const int64_t b = lo + 16 < A.nbytes ? lo + 16 : A.nbytes;
-        int k = (int)(a - lo), m = (int)(b - a);
-        uint64_t q = (uint64_t)(A.off + a) - ebase;
-        int i = runs_find(C, (int)n, q);
-        V4 acc = {0u, 0u, 0u, 0u};
-        if (UNPACK) {
+    const int nc = (int)n;
+    if (!UNPACK) {
+        // pack gathers one chunk at a time: issuing all four chunks' gathers
+        // together measured slower (many small loads per chunk)
+        for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) runs_chunk<false>(A, C, nc, ebase, eaddr, c);
+        return;
+    }
+    // unpack: a lane's chunks c + 256k (k < 4) per 1024-chunk step, packed
+    // loads first (stores do not wait)
+    for (int64_t s0 = c0; s0 < c1; s0 += 1024) {
+        const int64_t c = s0 + threadIdx.x;
+        const int64_t cend = min(s0 + 1024, c1);
+        V4 a0 = {0u, 0u, 0u, 0u}, a1 = a0, a2 = a0, a3 = a0;
+        uint32_t fast = 0;
+        if (runs_whole(A, c, cend)) {
             u32x4 v = __builtin_nontemporal_load(gptr((const u32x4 *)(A.packed - A.head + 16 * c)));
-            acc = V4{v.x, v.y, v.z, v.w};
+            a0 = V4{v.x, v.y, v.z, v.w};
+            fast |= 1u;
         }
-        while (m > 0) {
-            int64_t in = (int64_t)q - C.pre[i];
-            int64_t rem = C.pre[i + 1] - (int64_t)q;
-            int take = rem < m ? (int)rem : m;
-            const int64_t addr = eaddr + C.disp[i] + in;
-            if (UNPACK) {
-                scatter(acc, k, const_cast<uint8_t *>(typed) + addr, take);
-            } else {
-                if (take == 16) acc = load16(typed + addr);
-                else gather_part(acc, k, typed + addr, take);
-            }
-            q += take;
-            k += take;
-            m -= take;
-            i++;
+        if (runs_whole(A, c + 256, cend)) {
+            u32x4 v = __builtin_nontemporal_load(gptr((const u32x4 *)(A.packed - A.head + 16 * (c + 256))));
+            a1 = V4{v.x, v.y, v.z, v.w};
+            fast |= 2u;
         }
-        if (!UNPACK) {
-            uint8_t *dst = A.packed - A.head + 16 * c;
-            if (a == lo && b == lo + 16) {
-                u32x4 v = {acc.w0, acc.w1, acc.w2, acc.w3};
-                __builtin_nontemporal_store(v, gptr((u32x4 *)dst));
-            } else {
-                for (int j = (int)(a - lo); j < (int)(b - lo); j++) gptr(dst)[j] = (uint8_t)byte_at(acc, j);
-            }
+        if (runs_whole(A, c + 512, cend)) {
+            u32x4 v = __builtin_nontemporal_load(gptr((const u32x4 *)(A.packed - A.head + 16 * (c + 512))));
+            a2 = V4{v.x, v.y, v.z, v.w};
+            fast |= 4u;
+        }
+        if (runs_whole(A, c + 768, cend)) {
+            u32x4 v = __builtin_nontemporal_load(gptr((const u32x4 *)(A.packed - A.head + 16 * (c + 768))));
+            a3 = V4{v.x, v.y, v.z, v.w};
+            fast |= 8u;
+        }
+        if (fast & 1u) runs_scatter(A, C, nc, ebase, eaddr, c, a0);
+        if (fast & 2u) runs_scatter(A, C, nc, ebase, eaddr, c + 256, a1);
+        if (fast & 4u) runs_scatter(A, C, nc, ebase, eaddr, c + 512, a2);
+        if (fast & 8u) runs_scatter(A, C, nc, ebase, eaddr, c + 768, a3);
+#pragma unroll 1
+        for (int k = 0; k < 4; k++) {
+            const int64_t ck = c + 256 * k;
+            if (ck < cend && !((fast >> k) & 1u)) runs_chunk<true>(A, C, nc, ebase, eaddr, ck);
         }
     }
 }

@@ -55,3 +55,27 @@ def test_one_hip_runtime_per_process():
             "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n")
     out = subprocess.check_output([sys.executable, "-c", code], cwd=ROOT, text=True, timeout=300)
     assert out.strip().splitlines()[-1] == "1"
+
+
+def test_batch_config_validation():
+    """mdt_batch_set_config accepts exactly the documented knobs (no device
+    work: a batch allocates nothing until its first launch)."""
+    from paper_2402_12274_amd import mdt
+
+    b = mdt.Batch()
+    good = [(256, 0, 0, 0, 0), (4096, 16, 1, 1, 1), (1024, 4, 0, 0, 1), (512, 1, 1, 1, 0)]
+    for cfg in good:
+        b.set_config(mdt.BatchConfig(*cfg))
+        got = b.get_config()
+        assert tuple(getattr(got, f) for f, _ in got._fields_) == cfg
+    bad = [(128, 0, 0, 0, 0), (1000, 0, 0, 0, 0), (1024, -1, 0, 0, 0), (1024, 17, 0, 0, 0), (1024, 4, 2, 0, 0),
+           (1024, 4, 0, 2, 0), (1024, 4, 0, 0, 2), (1024, 4, 0, 0, -1)]
+    for cfg in bad:
+        try:
+            b.set_config(mdt.BatchConfig(*cfg))
+        except mdt.MdtError as e:
+            assert e.code == mdt.ERR_ARG
+        else:
+            raise AssertionError(f"config {cfg} accepted")
+        got = b.get_config()
+        assert tuple(getattr(got, f) for f, _ in got._fields_) == good[-1]
