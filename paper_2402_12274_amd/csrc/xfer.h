@@ -246,6 +246,13 @@ __device__ __forceinline__ bool pack_first(const DevLayout &L, const XferArgs &A
             Loc l2 = locate<KIND>(L, (uint64_t)(A.off + lo + t1), A.elem1);
             const uintptr_t a2 = (uintptr_t)(A.typed + l2.addr) - (uintptr_t)t1;  // chunk byte j of run 2 at a2 + j
             if (l2.rem >= 16 - t1 && (a2 & 3) == 0) {
+                if (t1 == 8 && ((a1 | a2) & 7) == 0) {
+                    // two 8-byte blocks (float64 at a stride): one request each
+                    const u32x2 x = *gptr((const u32x2 *)a1);
+                    const u32x2 y = *gptr((const u32x2 *)(a2 + 8));
+                    acc = V4{x.x, x.y, y.x, y.y};
+                    return true;
+                }
                 acc.w0 = *gptr((const uint32_t *)(0 < t1 ? a1 : a2));
                 acc.w1 = *gptr((const uint32_t *)(4 < t1 ? a1 + 4 : a2 + 4));
                 acc.w2 = *gptr((const uint32_t *)(8 < t1 ? a1 + 8 : a2 + 8));
