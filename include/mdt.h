@@ -276,12 +276,60 @@ MDT_API int mdt_typed_copy_enqueue(const void *src, mdt_count srccount, mdt_type
  * on s.  *actual_iov_len is returned immediately. */
 MDT_API int mdt_type_iov_enqueue(mdt_type t, mdt_count iov_offset, mdt_iov *dev_iov, mdt_count max_iov_len,
                                  const void *base, mdt_count *actual_iov_len, mdt_stream s, mdt_request *req);
-/* Complete a request: mdt_wait blocks; mdt_test sets *flag = 1 and frees
- * the request if it has completed, else *flag = 0.  Completed requests are
- * freed and set to MDT_REQUEST_NULL; a NULL request counts as complete. */
+/* Complete a request (from an enqueue or batch launch, or a generalized
+ * request): mdt_wait blocks; mdt_test sets *flag = 1 and frees the request
+ * if it has completed, else *flag = 0.  Completed requests are freed and
+ * set to MDT_REQUEST_NULL; a NULL request counts as complete.  mdt_waitall
+ * completes all n (NULL entries allowed), driving generalized requests
+ * together (one wait_fn call per group that shares it); on an error it
+ * returns the first error and leaves the requests it did not complete
+ * valid.  Server requests have their own calls (MDT_ERR_ARG here). */
 MDT_API int mdt_wait(mdt_request *req);
 MDT_API int mdt_test(mdt_request *req, int *flag);
 MDT_API int mdt_waitall(int n, mdt_request reqs[]);
+
+/* ---------------------------------------------------------------------
+ * Generalized requests (Generalized Requests section and its extension
+ * with poll and wait callbacks): a request for an asynchronous task the
+ * caller runs itself (its own kernel, I/O), completed by the same mdt_test,
+ * mdt_wait and mdt_waitall as the library's requests, with no progress
+ * thread of the caller's.  extra_state is the caller's and is passed to
+ * every callback; any callback may be NULL.
+ *   poll_fn(extra_state): called by mdt_test, mdt_wait and mdt_waitall an
+ *     unspecified number of times until the request is complete; it checks
+ *     the task and calls mdt_grequest_complete once the task has finished.
+ *   wait_fn(count, states, timeout): used by mdt_wait and mdt_waitall
+ *     instead of repeated polls, with the states of the incomplete requests
+ *     given to that call that share this wait_fn (in the order given); it
+ *     blocks until those tasks have finished or timeout seconds have passed
+ *     (timeout < 0: no limit), calling mdt_grequest_complete for each
+ *     finished task.  mdt_test uses poll_fn only.
+ *   query_fn(extra_state), then free_fn(extra_state): called once each when
+ *     a completion call returns the completed request (and frees it).
+ *   cancel_fn(extra_state, complete): called by mdt_cancel; complete is 1
+ *     when mdt_grequest_complete has already been called.
+ * A nonzero value returned by poll_fn or wait_fn ends the completion call
+ * with that value and leaves the request incomplete and valid; a nonzero
+ * value of query_fn or free_fn is returned by the completion call that
+ * freed the request.  With neither poll_fn nor wait_fn the task itself
+ * calls mdt_grequest_complete (from any thread) and mdt_wait blocks until
+ * it has.  Callbacks must not complete (test, wait) their own request. */
+typedef int (*mdt_grequest_query_fn)(void *extra_state);
+typedef int (*mdt_grequest_free_fn)(void *extra_state);
+typedef int (*mdt_grequest_cancel_fn)(void *extra_state, int complete);
+typedef int (*mdt_grequest_poll_fn)(void *extra_state);
+typedef int (*mdt_grequest_wait_fn)(int count, void *const *array_of_states, double timeout);
+MDT_API int mdt_grequest_start(mdt_grequest_query_fn query_fn, mdt_grequest_free_fn free_fn,
+                               mdt_grequest_cancel_fn cancel_fn, mdt_grequest_poll_fn poll_fn,
+                               mdt_grequest_wait_fn wait_fn, void *extra_state, mdt_request *req);
+/* Mark a generalized request's task finished (thread safe).  MDT_ERR_STATE
+ * if it was already marked, MDT_ERR_ARG if req is not a generalized
+ * request. */
+MDT_API int mdt_grequest_complete(mdt_request req);
+/* Cancel a generalized request: returns its cancel_fn's value (0 without
+ * one); the request must still be completed by mdt_test or mdt_wait.  Work
+ * enqueued on the GPU cannot be cancelled: MDT_ERR_ARG for other requests. */
+MDT_API int mdt_cancel(mdt_request req);
 
 /* ---------------------------------------------------------------------
  * Batches: many pack/unpack requests of mixed types and sizes executed by

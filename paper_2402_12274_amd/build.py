@@ -13,7 +13,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmdt.so")
 LOADGEN = os.path.join(HERE, "libmdt_loadgen.so")
 
-SOURCES = ["types.cpp", "compile.cpp", "api.cpp", "device.hip", "batch.hip", "batch_p0u0.hip", "batch_p0u1.hip",
+SOURCES = ["types.cpp", "compile.cpp", "api.cpp", "requests.cpp", "device.hip", "batch.hip", "batch_p0u0.hip", "batch_p0u1.hip",
            "batch_p1u0.hip", "batch_p1u1.hip", "server.cpp"]
 ARCH = os.environ.get("MDT_OFFLOAD_ARCH", "gfx950")
 

@@ -189,19 +189,6 @@ int copy_common(const void *src, int64_t srccount, mdt_type srctype, void *dst, 
     return MDT_SUCCESS;
 }
 
-int wait_request(mdt_request r)
-{
-    if (r->kind == REQ_EVENT) {
-        hipError_t e = hipEventSynchronize(r->ev);
-        if (e != hipSuccess) {
-            set_hip_error((int)e);
-            return MDT_ERR_HIP;
-        }
-        return MDT_SUCCESS;
-    }
-    return MDT_ERR_STATE;
-}
-
 void free_request(mdt_request r)
 {
     if (r->kind == REQ_EVENT) event_put(r->ev);
@@ -214,7 +201,6 @@ void free_request(mdt_request r)
 using namespace mdt;
 
 static bool valid_stream(mdt_stream s) { return s && s->magic == STREAM_MAGIC; }
-static bool valid_req(mdt_request r) { return r && r->magic == REQUEST_MAGIC; }
 
 extern "C" {
 
@@ -333,52 +319,6 @@ MDT_API int mdt_type_iov_enqueue(mdt_type t, mdt_count iov_offset, mdt_iov *dev_
     if (rc) return rc;
     *actual_iov_len = m;
     return MDT_SUCCESS;
-}
-
-MDT_API int mdt_wait(mdt_request *req)
-{
-    if (!req) return MDT_ERR_ARG;
-    if (*req == MDT_REQUEST_NULL) return MDT_SUCCESS;
-    if (!valid_req(*req)) return MDT_ERR_ARG;
-    int rc = wait_request(*req);
-    if (rc) return rc;
-    free_request(*req);
-    *req = MDT_REQUEST_NULL;
-    return MDT_SUCCESS;
-}
-
-MDT_API int mdt_test(mdt_request *req, int *flag)
-{
-    if (!req || !flag) return MDT_ERR_ARG;
-    if (*req == MDT_REQUEST_NULL) {
-        *flag = 1;
-        return MDT_SUCCESS;
-    }
-    if (!valid_req(*req) || (*req)->kind != REQ_EVENT) return MDT_ERR_ARG;
-    hipError_t e = hipEventQuery((*req)->ev);
-    if (e == hipErrorNotReady) {
-        *flag = 0;
-        return MDT_SUCCESS;
-    }
-    if (e != hipSuccess) {
-        set_hip_error((int)e);
-        return MDT_ERR_HIP;
-    }
-    free_request(*req);
-    *req = MDT_REQUEST_NULL;
-    *flag = 1;
-    return MDT_SUCCESS;
-}
-
-MDT_API int mdt_waitall(int n, mdt_request reqs[])
-{
-    if (n < 0 || (n > 0 && !reqs)) return MDT_ERR_ARG;
-    int first = MDT_SUCCESS;
-    for (int i = 0; i < n; i++) {
-        int rc = mdt_wait(&reqs[i]);
-        if (rc && !first) first = rc;
-    }
-    return first;
 }
 
 }  // extern "C"

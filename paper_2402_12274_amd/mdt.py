@@ -76,6 +76,13 @@ class ServerStats(C.Structure):
                 ("p99_run_us", C.c_double)]
 
 
+# generalized-request callbacks (include/mdt.h)
+GREQ_QUERY_FN = C.CFUNCTYPE(_INT, _P)
+GREQ_FREE_FN = C.CFUNCTYPE(_INT, _P)
+GREQ_CANCEL_FN = C.CFUNCTYPE(_INT, _P, _INT)
+GREQ_POLL_FN = C.CFUNCTYPE(_INT, _P)
+GREQ_WAIT_FN = C.CFUNCTYPE(_INT, _INT, C.POINTER(_P), C.c_double)
+
 _SIGS = {
     "mdt_basic": ([_INT], _P),
     "mdt_type_contiguous": ([_I64, _P, C.POINTER(_P)], _INT),
@@ -109,6 +116,10 @@ _SIGS = {
     "mdt_wait": ([C.POINTER(_P)], _INT),
     "mdt_test": ([C.POINTER(_P), C.POINTER(_INT)], _INT),
     "mdt_waitall": ([_INT, C.POINTER(_P)], _INT),
+    "mdt_grequest_start": ([GREQ_QUERY_FN, GREQ_FREE_FN, GREQ_CANCEL_FN, GREQ_POLL_FN, GREQ_WAIT_FN, _P,
+                            C.POINTER(_P)], _INT),
+    "mdt_grequest_complete": ([_P], _INT),
+    "mdt_cancel": ([_P], _INT),
     "mdt_batch_create": ([C.POINTER(_P)], _INT),
     "mdt_batch_free": ([C.POINTER(_P)], _INT),
     "mdt_batch_clear": ([_P], _INT),
@@ -363,6 +374,79 @@ class Request:
         f = C.c_int()
         check(_lib.mdt_test(C.byref(self.handle), C.byref(f)), "test")
         return bool(f.value)
+
+
+def waitall(reqs):
+    """mdt_waitall over Request objects (None entries allowed)."""
+    arr = (_P * len(reqs))(*[r.handle.value if r is not None else None for r in reqs])
+    rc = _lib.mdt_waitall(len(reqs), arr)
+    for r, h in zip(reqs, arr):
+        if r is not None:
+            r.handle = _P(h)
+    check(rc, "waitall")
+
+
+# live generalized requests by key (their extra_state), so the callbacks
+# and the Python state outlive the call that started them
+_GREQS = {}
+_GREQ_NEXT = [1]
+# one C wrapper per Python wait callable: requests that share the callable
+# share the C function pointer, so the library groups them into one call
+_WAIT_WRAPPERS = {}
+
+
+def _wait_wrapper(wait):
+    w = _WAIT_WRAPPERS.get(wait)
+    if w is None:
+        w = GREQ_WAIT_FN(lambda n, st, t: int(wait([_GREQS[st[i]] for i in range(n)], t) or 0))
+        _WAIT_WRAPPERS[wait] = w
+    return w
+
+
+class GRequest(Request):
+    """Generalized request (mdt_grequest_start) driven by Python callables.
+
+    poll(g) checks the task and calls g.complete() once it has finished;
+    wait(list_of_g, timeout) blocks on several of them at once; query(g),
+    free(g) and cancel(g, complete) follow include/mdt.h.  Each callable
+    returns None or 0 for success, or an int error code."""
+
+    def __init__(self, poll=None, wait=None, query=None, free=None, cancel=None, state=None):
+        super().__init__()
+        self.state = state
+        self.key = _GREQ_NEXT[0]
+        _GREQ_NEXT[0] += 1
+        rc = lambda v: int(v or 0)
+        me = self
+
+        def _free(_):
+            try:
+                return rc(free(me)) if free else 0
+            finally:
+                _GREQS.pop(me.key, None)
+
+        # an absent callback is a NULL function pointer (the type called
+        # with no argument)
+        cbs = (
+            GREQ_QUERY_FN(lambda _: rc(query(me))) if query else GREQ_QUERY_FN(),
+            GREQ_FREE_FN(_free),
+            GREQ_CANCEL_FN(lambda _, c: rc(cancel(me, bool(c)))) if cancel else GREQ_CANCEL_FN(),
+            GREQ_POLL_FN(lambda _: rc(poll(me))) if poll else GREQ_POLL_FN(),
+            _wait_wrapper(wait) if wait else GREQ_WAIT_FN(),
+        )
+        self._cbs = cbs
+        _GREQS[self.key] = self
+        try:
+            check(_lib.mdt_grequest_start(*cbs, _P(self.key), C.byref(self.handle)), "grequest_start")
+        except Exception:
+            _GREQS.pop(self.key, None)
+            raise
+
+    def complete(self):
+        check(_lib.mdt_grequest_complete(self.handle), "grequest_complete")
+
+    def cancel(self):
+        check(_lib.mdt_cancel(self.handle), "cancel")
 
 
 def mdt_pack_enqueue(inbuf: int, incount: int, t: Type, inoffset: int, outbuf: int, max_pack_bytes: int,
