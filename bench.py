@@ -11,7 +11,8 @@ per step), with all inputs resident in device memory before timing starts.
 
 Other workloads (--workload): particles (struct records x 4M), hindexed (1M
 irregular blocks in 2 GiB), contig (1 GiB contiguous), rows (an interior
-block of an 8192^2 float64 matrix), small (the 1024-element vector), serve
+block of an 8192^2 float64 matrix), darray (one rank's block-cyclic share of
+a 512^3 float64 array), small (the 1024-element vector), serve
 (the serving trace, served vs per-request) and batch4096 (4096 requests in
 one launch vs 4096 launches).  --mode batched (the default) runs each
 direction of a step as one batched launch (autotuned); --mode plain launches
@@ -92,7 +93,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="halo",
-                    choices=["halo", "particles", "hindexed", "contig", "rows", "small", "serve", "batch4096", "copy"])
+                    choices=["halo", "particles", "hindexed", "contig", "rows", "darray", "small", "serve", "batch4096",
+                             "copy"])
     ap.add_argument("--duration", type=float, default=15.0, help="serve: seconds of trace per replay")
     ap.add_argument("--rate", type=float, default=20000.0, help="serve: Poisson arrival rate (requests/s)")
     ap.add_argument("--sat-rate", type=float, default=150000.0,
@@ -138,6 +140,13 @@ def workload(name):
         return dict(desc="row-dominated subarray: interior [64, 8128)^2 block of a float64 8192x8192 array "
                          "(512 MiB): 8064 rows of 64,512 B, packed then unpacked per step",
                     src_bytes=n * n * 8, reqs=[("rows", spec, 1)], seed=inputs.DEFAULT_SEED + 4)
+    if name == "darray":
+        n = 512
+        spec = ("darray", 8, 5, [n, n, n], ["cyclic"] * 3, [16] * 3, [2, 2, 2], "C", inputs.DOUBLE)
+        return dict(desc="distributed array: rank 5's share of a float64 512^3 array (1 GiB) distributed "
+                         "cyclic(16) x cyclic(16) x cyclic(16) over a 2 x 2 x 2 process grid (128 MiB in "
+                         "128-byte runs), packed then unpacked per step",
+                    src_bytes=n ** 3 * 8, reqs=[("darray", spec, 1)], seed=inputs.DEFAULT_SEED + 5)
     if name == "small":
         return dict(desc="small vector: vector(1024, 1, 2, float64), 8 KiB packed from 16 KiB, packed then "
                          "unpacked per step", src_bytes=16384, reqs=[("vector", inputs.vector_small(), 1)],

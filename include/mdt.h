@@ -158,6 +158,29 @@ MDT_API int mdt_type_create_subarray(int ndims, const mdt_count sizes[], const m
 MDT_API int mdt_type_create_resized(mdt_type old, mdt_aint lb, mdt_aint extent, mdt_type *out);
 MDT_API int mdt_type_dup(mdt_type old, mdt_type *out);
 
+/* Distributed array (the constructor set the Derived Datatypes section
+ * relies on, as in MPI): the part of an nd-dimensional global array of
+ * `old` (sizes gsizes[], C or Fortran order) that process `rank` of a
+ * size-process grid owns.  The grid has psizes[k] processes along
+ * dimension k (their product is size) and ranks are laid out row-major
+ * over it.  Along dimension k the process at grid coordinate p owns:
+ *   MDT_DISTRIBUTE_NONE:   every index (psizes[k] must be 1);
+ *   MDT_DISTRIBUTE_BLOCK:  [p*b, min((p+1)*b, g)), b = dargs[k], or
+ *                          ceil(g / psizes[k]) for MDT_DISTRIBUTE_DFLT_DARG
+ *                          (b * psizes[k] >= g is required);
+ *   MDT_DISTRIBUTE_CYCLIC: the indices i with (i / k) mod psizes[k] == p,
+ *                          k = dargs[k], or 1 for MDT_DISTRIBUTE_DFLT_DARG.
+ * The typemap lists the owned elements in the array's order (last
+ * dimension fastest for C, first for Fortran), element i at
+ * linear(i) * extent(old); lb = 0, extent = prod(gsizes) * extent(old).
+ * Errors: MDT_ERR_ARG for an invalid grid, rank, distribution or
+ * argument, or 64-bit overflow. */
+enum { MDT_DISTRIBUTE_NONE = 0, MDT_DISTRIBUTE_BLOCK = 1, MDT_DISTRIBUTE_CYCLIC = 2 };
+#define MDT_DISTRIBUTE_DFLT_DARG (-1)
+MDT_API int mdt_type_create_darray(int size, int rank, int ndims, const mdt_count gsizes[], const int distribs[],
+                                   const int dargs[], const int psizes[], int order, mdt_type old,
+                                   mdt_type *out);
+
 /* Commit (worked example: committed before it is queried): compiles the
  * layout program and uploads its tables to the current HIP device, where
  * they stay resident until the last reference is freed.  Committing twice

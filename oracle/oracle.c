@@ -40,7 +40,8 @@ typedef enum {
     K_STRUCT,
     K_SUBARRAY,
     K_RESIZED,
-    K_DUP
+    K_DUP,
+    K_DARRAY
 } kind_t;
 
 #define ORC_MAX_DIMS 32
@@ -57,6 +58,7 @@ struct orc_type {
     orc_type *child;
     int nd, order;
     int64_t *sizes, *subs, *starts;
+    int64_t *own, *own_off; /* darray: owned indices of each dimension */
     int64_t rlb, rext;
     /* attributes */
     int64_t size, lb, ub, tlb, tub, align, nent;
@@ -186,6 +188,47 @@ static int for_each_copy(const orc_type *t, copy_cb cb, void *ctx)
             if (k < 0) return 0;
         }
     }
+    case K_DARRAY: {
+        /* distributed array: every tuple of owned indices (each dimension's
+         * owned indices in increasing order), the last dimension varying
+         * fastest for C order and the first for Fortran order; the copy
+         * sits at lin(tuple) * extent(c) over the global array. */
+        int nd = t->nd, k;
+        int64_t pos[ORC_MAX_DIMS], mult[ORC_MAX_DIMS];
+        int64_t E = extent_of(t->child);
+        for (k = 0; k < nd; k++) {
+            if (t->own_off[k + 1] == t->own_off[k]) return 0;
+            pos[k] = 0;
+        }
+        if (t->order == ORC_ORDER_C) {
+            int64_t m = 1;
+            for (k = nd - 1; k >= 0; k--) { mult[k] = m; if (!mul_ok(m, t->sizes[k], &m)) m = INT64_MAX; }
+        } else {
+            int64_t m = 1;
+            for (k = 0; k < nd; k++) { mult[k] = m; if (!mul_ok(m, t->sizes[k], &m)) m = INT64_MAX; }
+        }
+        for (;;) {
+            int64_t lin = 0;
+            for (k = 0; k < nd; k++) {
+                if (!mul_ok(t->own[t->own_off[k] + pos[k]], mult[k], &a) || !add_ok(lin, a, &lin)) return -1;
+            }
+            if (!mul_ok(lin, E, &s)) return -1;
+            if (cb(ctx, s, t->child)) return 1;
+            if (t->order == ORC_ORDER_C) {
+                for (k = nd - 1; k >= 0; k--) {
+                    if (++pos[k] < t->own_off[k + 1] - t->own_off[k]) break;
+                    pos[k] = 0;
+                }
+            } else {
+                for (k = 0; k < nd; k++) {
+                    if (++pos[k] < t->own_off[k + 1] - t->own_off[k]) break;
+                    pos[k] = 0;
+                }
+                if (k == nd) k = -1;
+            }
+            if (k < 0) return 0;
+        }
+    }
     case K_RESIZED:
     case K_DUP:
         /* the typemap of the child, unchanged */
@@ -257,7 +300,8 @@ static int compute_attrs(orc_type *t)
             }
         }
         break;
-    case K_SUBARRAY: {
+    case K_SUBARRAY:
+    case K_DARRAY: {
         /* bounds are those of the whole array: [0, prod(sizes) * extent) */
         int64_t m = 1;
         int k;
@@ -314,6 +358,8 @@ void orc_release(orc_type *t)
     free(t->sizes);
     free(t->subs);
     free(t->starts);
+    free(t->own);
+    free(t->own_off);
     free(t);
 }
 
@@ -491,6 +537,67 @@ orc_type *orc_subarray(int nd, const int64_t *sizes, const int64_t *subsizes, co
     if (!t->sizes || !t->subs || !t->starts) {
         orc_release(t);
         return fail(err, ORC_ERR_NOMEM);
+    }
+    t->child = c;
+    retain(c);
+    return finish(t, err);
+}
+
+/* Distributed array (MPI semantics): the elements of an nd-dimensional
+ * global array that process `rank` of a row-major process grid owns.  Each
+ * dimension's owned indices are found by asking, index by index, which grid
+ * coordinate owns it: block distribution, owner = i / b (b = darg, or
+ * ceil(g / p) by default); cyclic, owner = (i / k) mod p (k = darg, or 1);
+ * none, the single coordinate 0. */
+orc_type *orc_darray(int size, int rank, int nd, const int64_t *gsizes, const int *distribs, const int *dargs,
+                     const int *psizes, int order, orc_type *c, int *err)
+{
+    orc_type *t;
+    int64_t coord[ORC_MAX_DIMS], nproc = 1, total = 0, i;
+    int k, r;
+    if (nd < 1 || nd > ORC_MAX_DIMS || !c || !gsizes || !distribs || !dargs || !psizes) return fail(err, ORC_ERR_ARG);
+    if (order != ORC_ORDER_C && order != ORC_ORDER_FORTRAN) return fail(err, ORC_ERR_ARG);
+    if (size < 1 || rank < 0 || rank >= size) return fail(err, ORC_ERR_ARG);
+    for (k = 0; k < nd; k++) {
+        if (gsizes[k] < 1 || psizes[k] < 1 || !mul_ok(nproc, psizes[k], &nproc)) return fail(err, ORC_ERR_ARG);
+        if (dargs[k] != ORC_DFLT_DARG && dargs[k] < 1) return fail(err, ORC_ERR_ARG);
+        if (distribs[k] == ORC_DISTRIBUTE_NONE && psizes[k] != 1) return fail(err, ORC_ERR_ARG);
+        if (distribs[k] == ORC_DISTRIBUTE_BLOCK && dargs[k] != ORC_DFLT_DARG &&
+            (int64_t)dargs[k] * psizes[k] < gsizes[k])
+            return fail(err, ORC_ERR_ARG);
+        if (distribs[k] != ORC_DISTRIBUTE_NONE && distribs[k] != ORC_DISTRIBUTE_BLOCK &&
+            distribs[k] != ORC_DISTRIBUTE_CYCLIC)
+            return fail(err, ORC_ERR_ARG);
+        if (!add_ok(total, gsizes[k], &total)) return fail(err, ORC_ERR_ARG);
+    }
+    if (nproc != size) return fail(err, ORC_ERR_ARG);
+    r = rank;
+    for (k = nd - 1; k >= 0; k--) {
+        coord[k] = r % psizes[k];
+        r /= psizes[k];
+    }
+    t = new_node(K_DARRAY);
+    if (!t) return fail(err, ORC_ERR_NOMEM);
+    t->nd = nd;
+    t->order = order;
+    t->sizes = dup_arr(gsizes, nd);
+    t->own = (int64_t *)malloc((size_t)(total > 0 ? total : 1) * sizeof(int64_t));
+    t->own_off = (int64_t *)malloc((size_t)(nd + 1) * sizeof(int64_t));
+    if (!t->sizes || !t->own || !t->own_off) {
+        orc_release(t);
+        return fail(err, ORC_ERR_NOMEM);
+    }
+    t->own_off[0] = 0;
+    for (k = 0; k < nd; k++) {
+        int64_t g = gsizes[k], p = psizes[k], n = t->own_off[k];
+        int64_t b = dargs[k] == ORC_DFLT_DARG ? (distribs[k] == ORC_DISTRIBUTE_BLOCK ? (g + p - 1) / p : 1) : dargs[k];
+        for (i = 0; i < g; i++) {
+            int64_t owner = 0;
+            if (distribs[k] == ORC_DISTRIBUTE_BLOCK) owner = i / b;
+            else if (distribs[k] == ORC_DISTRIBUTE_CYCLIC) owner = (i / b) % p;
+            if (owner == coord[k]) t->own[n++] = i;
+        }
+        t->own_off[k + 1] = n;
     }
     t->child = c;
     retain(c);

@@ -51,6 +51,13 @@ orc_type *orc_hindexed_block(int64_t n, int64_t bl, const int64_t *disp_bytes, o
 orc_type *orc_struct(int64_t n, const int64_t *bl, const int64_t *disp_bytes, orc_type *const *c, int *err);
 orc_type *orc_subarray(int nd, const int64_t *sizes, const int64_t *subsizes, const int64_t *starts,
                        int order, orc_type *c, int *err);
+/* distributions of orc_darray */
+#define ORC_DISTRIBUTE_NONE 0
+#define ORC_DISTRIBUTE_BLOCK 1
+#define ORC_DISTRIBUTE_CYCLIC 2
+#define ORC_DFLT_DARG (-1)
+orc_type *orc_darray(int size, int rank, int nd, const int64_t *gsizes, const int *distribs, const int *dargs,
+                     const int *psizes, int order, orc_type *c, int *err);
 orc_type *orc_resized(orc_type *c, int64_t lb, int64_t extent, int *err);
 orc_type *orc_dup(orc_type *c, int *err);
 void orc_release(orc_type *t);

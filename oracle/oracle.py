@@ -78,6 +78,8 @@ def load():
         "orc_hindexed_block": ([_I64, _I64, _I64P, _P, errp], _P),
         "orc_struct": ([_I64, _I64P, _I64P, C.POINTER(_P), errp], _P),
         "orc_subarray": ([C.c_int, _I64P, _I64P, _I64P, C.c_int, _P, errp], _P),
+        "orc_darray": ([C.c_int, C.c_int, C.c_int, _I64P, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                        C.POINTER(C.c_int), C.c_int, _P, errp], _P),
         "orc_resized": ([_P, _I64, _I64, errp], _P),
         "orc_dup": ([_P, errp], _P),
         "orc_release": ([_P], None),
@@ -232,6 +234,19 @@ def build_type(spec) -> OType:
         t, tp = _arr(starts)
         o = {"C": 0, "F": 1}.get(order, 7)
         return _mk(lib.orc_subarray(s.size, sp, up, tp, o, c.ptr, ep), err)
+    if kind == "darray":
+        # ("darray", size, rank, gsizes, distribs ("none"|"block"|"cyclic"),
+        #  dargs (int, or None for the default), psizes, order, child)
+        _, size, rank, gsizes, distribs, dargs, psizes, order, child = spec
+        c = build_type(child)
+        g, gp = _arr(gsizes)
+        nd = g.size
+        ints = lambda v: (C.c_int * max(1, nd))(*v)
+        dist = ints([{"none": 0, "block": 1, "cyclic": 2}.get(d, 9) for d in distribs])
+        darg = ints([-1 if a is None else a for a in dargs])
+        ps = ints(psizes)
+        o = {"C": 0, "F": 1}.get(order, 7)
+        return _mk(lib.orc_darray(size, rank, nd, gp, dist, darg, ps, o, c.ptr, ep), err)
     if kind == "resized":
         _, lb, extent, child = spec
         c = build_type(child)

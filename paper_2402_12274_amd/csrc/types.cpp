@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "core.h"
 
@@ -438,6 +439,124 @@ MDT_API int mdt_type_dup(mdt_type old, mdt_type *out)
         d->ub = c->ub;
     }
     return rc;
+}
+
+// Distributed array: the indices each dimension owns are a list of blocks
+// (one for a block or undistributed dimension, several for a cyclic one).
+// With one block per dimension the result is the subarray of those blocks;
+// otherwise it is built one dimension at a time, fastest first: an hindexed
+// of the blocks over the faster dimensions' type, resized to the whole
+// dimension, so the next dimension steps over complete hyperplanes.
+MDT_API int mdt_type_create_darray(int size, int rank, int ndims, const mdt_count gsizes[], const int distribs[],
+                                   const int dargs[], const int psizes[], int order, mdt_type old, mdt_type *out)
+{
+    CHECK_TYPE(old);
+    if (!out || ndims < 1 || ndims > 32 || !gsizes || !distribs || !dargs || !psizes) return MDT_ERR_ARG;
+    if (order != MDT_ORDER_C && order != MDT_ORDER_FORTRAN) return MDT_ERR_ARG;
+    if (size < 1 || rank < 0 || rank >= size) return MDT_ERR_ARG;
+    int64_t nproc = 1;
+    for (int k = 0; k < ndims; k++) {
+        if (gsizes[k] < 1 || psizes[k] < 1 || !mul_ok(nproc, psizes[k], &nproc)) return MDT_ERR_ARG;
+    }
+    if (nproc != size) return MDT_ERR_ARG;
+    // grid coordinates: ranks are row-major over the process grid
+    std::vector<int64_t> coord(ndims);
+    for (int k = ndims - 1, r = rank; k >= 0; k--) {
+        coord[k] = r % psizes[k];
+        r /= psizes[k];
+    }
+    // owned blocks (start, length) of every dimension, in increasing order
+    std::vector<std::vector<std::pair<int64_t, int64_t>>> blocks(ndims);
+    bool single = true;
+    for (int k = 0; k < ndims; k++) {
+        const int64_t g = gsizes[k], P = psizes[k], c = coord[k];
+        const int d = dargs[k];
+        if (d != MDT_DISTRIBUTE_DFLT_DARG && d < 1) return MDT_ERR_ARG;
+        if (distribs[k] == MDT_DISTRIBUTE_NONE) {
+            if (P != 1) return MDT_ERR_ARG;
+            blocks[k].push_back({0, g});
+        } else if (distribs[k] == MDT_DISTRIBUTE_BLOCK) {
+            const int64_t b = d == MDT_DISTRIBUTE_DFLT_DARG ? (g + P - 1) / P : d;
+            int64_t cover;
+            if (!mul_ok(b, P, &cover) || cover < g) return MDT_ERR_ARG;
+            const int64_t st = c * b;
+            if (st < g) blocks[k].push_back({st, std::min(b, g - st)});
+        } else if (distribs[k] == MDT_DISTRIBUTE_CYCLIC) {
+            const int64_t b = d == MDT_DISTRIBUTE_DFLT_DARG ? 1 : d;
+            int64_t step;
+            if (!mul_ok(b, P, &step)) return MDT_ERR_ARG;
+            for (int64_t st = c * b; st < g; st += step) {
+                blocks[k].push_back({st, std::min(b, g - st)});
+                if (g - st <= step) break;
+            }
+        } else {
+            return MDT_ERR_ARG;
+        }
+        single = single && blocks[k].size() <= 1;
+    }
+    if (single) {
+        std::vector<mdt_count> sub(ndims), st(ndims);
+        for (int k = 0; k < ndims; k++) {
+            sub[k] = blocks[k].empty() ? 0 : blocks[k][0].second;
+            st[k] = blocks[k].empty() ? 0 : blocks[k][0].first;
+        }
+        return mdt_type_create_subarray(ndims, gsizes, sub.data(), st.data(), order, old, out);
+    }
+    // fastest dimension first; cur holds a reference the loop owns (old is
+    // borrowed until the first step replaces it).  A dimension's full
+    // blocks are equally spaced, so they are one strided vector (the layout
+    // compiler turns it into a loop), placed at the first block; a shorter
+    // last block follows it as a second struct member.
+    mdt_type cur = old;
+    bool owned = false;
+    int64_t E = as_node(old)->extent();
+    int rc = MDT_SUCCESS;
+    for (int i = 0; i < ndims && rc == MDT_SUCCESS; i++) {
+        const int k = order == MDT_ORDER_C ? ndims - 1 - i : i;
+        const auto &B = blocks[k];
+        const size_t nb = B.size();
+        int64_t span;
+        if (!mul_ok(gsizes[k], E, &span)) rc = MDT_ERR_ARG;
+        mdt_type placed = MDT_TYPE_NULL;  // the dimension's owned blocks of cur, at their displacements
+        if (rc == MDT_SUCCESS && nb <= 1) {
+            mdt_count bl = nb ? B[0].second : 0;
+            mdt_aint disp = 0;
+            if (nb && !mul_ok(B[0].first, E, &disp)) rc = MDT_ERR_ARG;
+            if (rc == MDT_SUCCESS) rc = mdt_type_create_hindexed((mdt_count)nb, &bl, &disp, cur, &placed);
+        } else if (rc == MDT_SUCCESS) {
+            const int64_t kb = B[0].second;                  // block length
+            const size_t nfull = B.back().second == kb ? nb : nb - 1;
+            int64_t stride, d0;
+            if (!mul_ok(B[1].first - B[0].first, E, &stride) || !mul_ok(B[0].first, E, &d0)) rc = MDT_ERR_ARG;
+            mdt_type vec = MDT_TYPE_NULL;
+            if (rc == MDT_SUCCESS) rc = mdt_type_create_hvector((mdt_count)nfull, kb, stride, cur, &vec);
+            if (rc == MDT_SUCCESS && nfull == nb) {
+                mdt_count one = 1;
+                rc = mdt_type_create_hindexed(1, &one, &d0, vec, &placed);
+            } else if (rc == MDT_SUCCESS) {
+                int64_t dt;
+                if (!mul_ok(B.back().first, E, &dt)) rc = MDT_ERR_ARG;
+                mdt_count bl2[2] = {1, B.back().second};
+                mdt_aint disp2[2] = {d0, dt};
+                mdt_type kids[2] = {vec, cur};
+                if (rc == MDT_SUCCESS) rc = mdt_type_create_struct(2, bl2, disp2, kids, &placed);
+            }
+            if (vec) mdt_type_free(&vec);
+        }
+        mdt_type r = MDT_TYPE_NULL;
+        if (rc == MDT_SUCCESS) rc = mdt_type_create_resized(placed, 0, span, &r);
+        if (placed) mdt_type_free(&placed);
+        if (owned) mdt_type_free(&cur);
+        cur = r;
+        owned = true;
+        E = span;
+    }
+    if (rc != MDT_SUCCESS) {
+        if (owned && cur) mdt_type_free(&cur);
+        return rc;
+    }
+    *out = cur;
+    return MDT_SUCCESS;
 }
 
 MDT_API int mdt_type_commit(mdt_type *t)

@@ -36,6 +36,7 @@ _lib = C.CDLL(LIB_PATH)
 # error codes (include/mdt.h)
 SUCCESS, ERR_ARG, ERR_TYPE, ERR_COUNT, ERR_TRUNCATE, ERR_OVERLAP, ERR_NO_MEM, ERR_HIP, ERR_AGAIN, ERR_STATE = range(10)
 ORDER_C, ORDER_FORTRAN = 0, 1
+DISTRIBUTE_NONE, DISTRIBUTE_BLOCK, DISTRIBUTE_CYCLIC, DISTRIBUTE_DFLT_DARG = 0, 1, 2, -1
 BASIC_CODES = {
     "BYTE": 0, "CHAR": 1, "INT8": 2, "UINT8": 3, "INT16": 4, "UINT16": 5, "INT32": 6, "UINT32": 7,
     "INT": 8, "FLOAT": 9, "INT64": 10, "UINT64": 11, "DOUBLE": 12,
@@ -94,6 +95,8 @@ _SIGS = {
     "mdt_type_create_hindexed_block": ([_I64, _I64, _I64P, _P, C.POINTER(_P)], _INT),
     "mdt_type_create_struct": ([_I64, _I64P, _I64P, C.POINTER(_P), C.POINTER(_P)], _INT),
     "mdt_type_create_subarray": ([_INT, _I64P, _I64P, _I64P, _INT, _P, C.POINTER(_P)], _INT),
+    "mdt_type_create_darray": ([_INT, _INT, _INT, _I64P, C.POINTER(_INT), C.POINTER(_INT), C.POINTER(_INT), _INT, _P,
+                                C.POINTER(_P)], _INT),
     "mdt_type_create_resized": ([_P, _I64, _I64, C.POINTER(_P)], _INT),
     "mdt_type_dup": ([_P, C.POINTER(_P)], _INT),
     "mdt_type_commit": ([C.POINTER(_P)], _INT),
@@ -308,6 +311,19 @@ def _build(spec) -> Type:
         t, tp = _arr(starts)
         o = {"C": ORDER_C, "F": ORDER_FORTRAN}.get(order, 7)
         return _new(_lib.mdt_type_create_subarray, s.size, sp, up, tp, o, c.h, what=k)
+    if k == "darray":
+        # ("darray", size, rank, gsizes, distribs ("none"|"block"|"cyclic"),
+        #  dargs (int, or None for the default), psizes, order, child)
+        _, size, rank, gsizes, distribs, dargs, psizes, order, child = spec
+        c = _build(child)
+        g, gp = _arr(gsizes)
+        nd = g.size
+        ints = lambda v: (_INT * max(1, nd))(*v)
+        dist = ints([{"none": DISTRIBUTE_NONE, "block": DISTRIBUTE_BLOCK, "cyclic": DISTRIBUTE_CYCLIC}.get(d, 9)
+                     for d in distribs])
+        darg = ints([DISTRIBUTE_DFLT_DARG if a is None else a for a in dargs])
+        o = {"C": ORDER_C, "F": ORDER_FORTRAN}.get(order, 7)
+        return _new(_lib.mdt_type_create_darray, size, rank, nd, gp, dist, darg, ints(psizes), o, c.h, what=k)
     if k == "resized":
         _, lb, ext, child = spec
         c = _build(child)

@@ -281,3 +281,48 @@ def test_device_flatten_matches_oracle(mdt):
             h = out.cpu().numpy()[: 2 * got].reshape(-1, 2)
             assert np.array_equal(h[:, 0] - base, ob) and np.array_equal(h[:, 1], ol), spec
     assert ctypes.sizeof(mdt.Iov) == 16
+
+
+def test_darray_random_small(mdt):
+    """Random distributed arrays (every distribution, both orders, gapped
+    element types): full and partial packs at odd output alignments and
+    unpack into canaries, against the oracle."""
+    from typegen import darray_specs
+
+    for i, spec in enumerate(darray_specs(123, 60)):
+        note(f"darray small {i}: {spec}")
+        t = mdt.build_type(spec)
+        o = obuild(spec)
+        a = o.attrs()
+        if a["size"] == 0:
+            continue
+        size = a["extent"] + 64
+        host = inputs.random_bytes(size, seed=500 + i)
+        src = to_dev(host)
+        full = o.pack(host, 32, 1)
+        for shift in (0, 5):
+            got = _pack_dev(mdt, t, src, 32, 1, 0, -1, shift)
+            assert first_diff(got, full) is None, (spec, shift)
+        got = _pack_dev(mdt, t, src, 32, 1, a["size"] // 3, 11, 3)
+        assert first_diff(got, o.pack(host, 32, 1, a["size"] // 3, 11)) is None, spec
+        canary = np.full(size, 0x5A, np.uint8)
+        exp = canary.copy()
+        o.unpack(full, exp, 32, 1)
+        dst = to_dev(canary)
+        mdt.mdt_unpack(to_dev(full).data_ptr(), full.size, dst.data_ptr() + 32, 1, t, 0)
+        assert first_diff(to_host(dst), exp) is None, spec
+
+
+def test_darray_midsize(mdt):
+    """Block-cyclic 3-D distributions of a 96 x 80 x 64 float64 array (and
+    particle records on a 2-D grid) over several ranks: many tiles, ragged
+    ends, chunked partial packs and unpacks."""
+    D = ("basic", "DOUBLE")
+    gs = [96, 80, 64]
+    cases = [("darray", 8, r, gs, ["cyclic", "block", "cyclic"], [4, None, 8], [2, 2, 2], "C", D) for r in (0, 5, 7)]
+    cases += [("darray", 6, r, gs, ["block", "cyclic", "none"], [None, 3, None], [3, 2, 1], "F", D) for r in (1, 4)]
+    cases += [("darray", 4, 3, [300, 250], ["cyclic", "cyclic"], [7, None], [2, 2], "C", inputs.particle_struct())]
+    for i, spec in enumerate(cases):
+        note(f"darray midsize {i}: {spec[1:8]}")
+        o = obuild(spec)
+        _layout_case(mdt, spec, 1, o.attrs()["extent"], 0, seed=700 + i, chunk=(1 << 15) + 7)

@@ -162,3 +162,33 @@ def test_layout_info_reports_the_program():
     info = mdt.LayoutInfo()
     assert mdt._lib.mdt_type_layout_info(raw, ctypes.byref(info)) == mdt.ERR_TYPE
     assert mdt._lib.mdt_type_free(ctypes.byref(raw)) == 0
+
+
+def test_darray_matches_oracle():
+    """Distributed arrays through the library (built from subarray, or from
+    hindexed and resized per dimension) against the oracle's enumeration."""
+    from typegen import darray_specs
+
+    for spec in darray_specs(77, 150):
+        t = mdt.build_type(spec)
+        o = obuild(spec)
+        _cmp_attrs(t, o)
+        _cmp_segments(t, o, probe_all=False)
+
+
+def test_darray_errors():
+    D = ("basic", "DOUBLE")
+    bad = [
+        ("darray", 4, 0, [8, 8], ["block", "block"], [None, None], [2, 3], "C", D),
+        ("darray", 4, -1, [8, 8], ["block", "block"], [None, None], [2, 2], "C", D),
+        ("darray", 2, 0, [8], ["none"], [None], [2], "C", D),
+        ("darray", 2, 0, [8], ["block"], [3], [2], "C", D),
+        ("darray", 2, 0, [8], ["cyclic"], [0], [2], "C", D),
+        ("darray", 2, 0, [8], ["diagonal"], [None], [2], "C", D),
+        ("darray", 2, 0, [0], ["block"], [None], [2], "C", D),
+        ("darray", 2, 0, [8], ["block"], [None], [2], "Z", D),
+    ]
+    for spec in bad:
+        with pytest.raises(mdt.MdtError) as e:
+            mdt.build_type(spec)
+        assert e.value.code == mdt.ERR_ARG, spec

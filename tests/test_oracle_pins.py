@@ -333,3 +333,100 @@ def test_multithreaded_pack_equals_single():
     one = t.pack(buf, 0, count)
     assert np.array_equal(t.pack(buf, 0, count, nthreads=4), one)
     assert np.array_equal(t.pack(buf, 0, count, 123457, 1 << 20, nthreads=3), one[123457:123457 + (1 << 20)])
+
+
+# ---------------------------------------------------------------------------
+# distributed arrays: pinned by properties the definition implies, not by
+# restating its ownership rule
+
+def _darray_labels(spec):
+    """Linear element indices that (1 x spec) packs, for an INT32 element:
+    the buffer holds each element's own linear index."""
+    _, size, rank, gs, ds, da, ps, order, _ = spec
+    s = ("darray", size, rank, gs, ds, da, ps, order, ("basic", "INT32"))
+    t = build_type(s)
+    total = int(np.prod(gs))
+    buf = np.arange(total, dtype=np.int32).view(np.uint8)
+    return np.frombuffer(t.pack(buf, 0, 1).tobytes(), dtype=np.int32), t
+
+
+def test_darray_ranks_partition_the_array():
+    """Over all ranks of the grid every element is owned exactly once, and
+    each rank lists its elements in increasing linear order (row-major for
+    C, column-major for Fortran)."""
+    from typegen import darray_specs
+
+    for spec in darray_specs(31, 60):
+        _, size, _, gs, ds, da, ps, order, _ = spec
+        seen = []
+        for r in range(size):
+            lab, t = _darray_labels(("darray", size, r, gs, ds, da, ps, order, None))
+            assert np.all(np.diff(lab) > 0), spec
+            a = t.attrs()
+            assert a["lb"] == 0 and a["extent"] == 4 * int(np.prod(gs))
+            seen.append(lab)
+        allv = np.sort(np.concatenate(seen))
+        assert np.array_equal(allv, np.arange(int(np.prod(gs)))), spec
+
+
+def test_darray_block_is_a_subarray():
+    """With one grid coordinate per dimension (psizes all 1) a block or
+    undistributed darray is the whole array, and a block distribution of
+    one dimension over p processes gives p consecutive slabs in rank
+    order."""
+    for order in ("C", "F"):
+        lab, _ = _darray_labels(("darray", 1, 0, [5, 3, 4], ["block", "none", "block"], [None] * 3, [1, 1, 1],
+                                 order, None))
+        lin = np.arange(60).reshape([5, 3, 4], order=order).ravel(order=order)
+        assert np.array_equal(lab, lin)
+    # slabs: the C-order rows of a 10 x 6 array over 4 processes (3, 3, 3, 1 rows)
+    got = [_darray_labels(("darray", 4, r, [10, 6], ["block", "none"], [None, None], [4, 1], "C", None))[0]
+           for r in range(4)]
+    sub = [build_type(("subarray", [10, 6], [n, 6], [s, 0], "C", ("basic", "INT32")))
+           for s, n in ((0, 3), (3, 3), (6, 3), (9, 1))]
+    buf = np.arange(60, dtype=np.int32).view(np.uint8)
+    for g_, s_ in zip(got, sub):
+        assert np.array_equal(g_, np.frombuffer(s_.pack(buf, 0, 1).tobytes(), dtype=np.int32))
+
+
+def test_darray_cyclic_matches_numpy_reshape():
+    """Cyclic(k) over p processes when k*p divides the dimension: rank c owns
+    column c of the (g/(k p), p, k) reshape of the index range; with a
+    second, undistributed dimension the rows are those indices."""
+    for g_, k, p in ((24, 2, 3), (12, 1, 4), (30, 5, 3), (8, 4, 2)):
+        for c in range(p):
+            lab, _ = _darray_labels(("darray", p, c, [g_], ["cyclic"], [k], [p], "C", None))
+            assert np.array_equal(lab, np.arange(g_).reshape(g_ // (k * p), p, k)[:, c, :].ravel())
+            lab, _ = _darray_labels(("darray", p, c, [g_, 5], ["cyclic", "none"], [k, None], [p, 1], "C", None))
+            rows = np.arange(g_).reshape(g_ // (k * p), p, k)[:, c, :].ravel()
+            assert np.array_equal(lab, (rows[:, None] * 5 + np.arange(5)[None, :]).ravel())
+
+
+def test_darray_error_rules():
+    D = ("basic", "DOUBLE")
+    bad = [
+        ("darray", 4, 0, [8, 8], ["block", "block"], [None, None], [2, 3], "C", D),  # grid of 6 != 4
+        ("darray", 4, 4, [8, 8], ["block", "block"], [None, None], [2, 2], "C", D),  # rank out of range
+        ("darray", 2, 0, [8], ["none"], [None], [2], "C", D),                        # none over 2
+        ("darray", 2, 0, [8], ["block"], [3], [2], "C", D),                          # 3 * 2 < 8
+        ("darray", 2, 0, [8], ["cyclic"], [0], [2], "C", D),                         # darg 0
+        ("darray", 2, 0, [8], ["diagonal"], [None], [2], "C", D),                    # no such distribution
+        ("darray", 2, 0, [0], ["block"], [None], [2], "C", D),                       # empty dimension
+        ("darray", 2, 0, [8], ["block"], [None], [2], "Z", D),                       # order
+    ]
+    for spec in bad:
+        with pytest.raises(OracleError):
+            build_type(spec)
+
+
+def test_darray_default_arguments():
+    """The default distribution argument is 1 for cyclic and ceil(g / p)
+    for block (MPI's defaults)."""
+    for g_, p in ((10, 3), (7, 7), (9, 2), (1, 4)):
+        for c in range(p):
+            d, _ = _darray_labels(("darray", p, c, [g_], ["cyclic"], [None], [p], "C", None))
+            e, _ = _darray_labels(("darray", p, c, [g_], ["cyclic"], [1], [p], "C", None))
+            assert np.array_equal(d, e)
+            d, _ = _darray_labels(("darray", p, c, [g_], ["block"], [None], [p], "C", None))
+            e, _ = _darray_labels(("darray", p, c, [g_], ["block"], [-(-g_ // p)], [p], "C", None))
+            assert np.array_equal(d, e)

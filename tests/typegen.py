@@ -84,3 +84,34 @@ def buffer_for(tm, count: int, pad: int = 16):
     lo = min(r * tm.extent + tm.true_lb for r in range(count))
     hi = max(r * tm.extent + tm.true_ub for r in range(count))
     return hi - lo + 2 * pad, pad - lo
+
+
+def darray_specs(seed: int, n: int, max_g: int = 12):
+    """Random distributed-array specs: 1-3 dimensions, every distribution,
+    default and explicit distribution arguments, both orders, basic and
+    derived (gapped) element types, any rank of the process grid."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    elems = [("basic", "DOUBLE"), ("basic", "INT32"), ("basic", "BYTE"), ("basic", "INT16"),
+             ("vector", 2, 1, 3, ("basic", "INT32")), ("contiguous", 3, ("basic", "INT16"))]
+    out = []
+    while len(out) < n:
+        nd = int(g.integers(1, 4))
+        gs = [int(g.integers(1, max_g + 1)) for _ in range(nd)]
+        ds, da, ps = [], [], []
+        for k in range(nd):
+            d = ["none", "block", "cyclic"][int(g.integers(0, 3))]
+            p = 1 if d == "none" else int(g.integers(1, 5))
+            a = None
+            if d == "block" and g.random() < 0.5:
+                a = -(-gs[k] // p) + int(g.integers(0, 3))  # any block size that covers the dimension
+            elif d == "cyclic" and g.random() < 0.6:
+                a = int(g.integers(1, 5))
+            ds.append(d)
+            da.append(a)
+            ps.append(p)
+        size = int(np.prod(ps))
+        rank = int(g.integers(0, size))
+        order = "C" if g.random() < 0.5 else "F"
+        elem = elems[int(g.integers(0, len(elems)))]
+        out.append(("darray", size, rank, gs, ds, da, ps, order, elem))
+    return out
