@@ -181,6 +181,38 @@ MDT_API int mdt_type_create_darray(int size, int rank, int ndims, const mdt_coun
                                    const int dargs[], const int psizes[], int order, mdt_type old,
                                    mdt_type *out);
 
+/* Type envelope and contents (MPI_Type_get_envelope / get_contents: the
+ * constructor call a type was made with, so a type can be described,
+ * serialized and rebuilt).  The envelope gives the combiner and the lengths
+ * of the three argument lists; the contents fill them:
+ *   NAMED (a predefined type): no contents (get_contents: MDT_ERR_ARG)
+ *   DUP:            types {old}
+ *   CONTIGUOUS:     ints {count}; types {old}
+ *   VECTOR:         ints {count, blocklength, stride}; types {old}
+ *   HVECTOR:        ints {count, blocklength}; addrs {stride}; types {old}
+ *   INDEXED:        ints {count, bl[count], disp[count]}; types {old}
+ *   HINDEXED:       ints {count, bl[count]}; addrs {disp[count]}; types {old}
+ *   INDEXED_BLOCK:  ints {count, blocklength, disp[count]}; types {old}
+ *   HINDEXED_BLOCK: ints {count, blocklength}; addrs {disp[count]}; types {old}
+ *   STRUCT:         ints {count, bl[count]}; addrs {disp[count]}; types[count]
+ *   SUBARRAY:       ints {ndims, sizes[], subsizes[], starts[], order}; types {old}
+ *   DARRAY:         ints {size, rank, ndims, gsizes[], distribs[], dargs[],
+ *                   psizes[], order}; types {old}
+ *   RESIZED:        addrs {lb, extent}; types {old}
+ * Returned derived types are new references (release each with
+ * mdt_type_free); predefined ones are returned as themselves.  Errors:
+ * MDT_ERR_ARG if a max_* is below the envelope's count (nothing written). */
+enum {
+    MDT_COMBINER_NAMED = 0, MDT_COMBINER_DUP, MDT_COMBINER_CONTIGUOUS, MDT_COMBINER_VECTOR, MDT_COMBINER_HVECTOR,
+    MDT_COMBINER_INDEXED, MDT_COMBINER_HINDEXED, MDT_COMBINER_INDEXED_BLOCK, MDT_COMBINER_HINDEXED_BLOCK,
+    MDT_COMBINER_STRUCT, MDT_COMBINER_SUBARRAY, MDT_COMBINER_DARRAY, MDT_COMBINER_RESIZED
+};
+MDT_API int mdt_type_get_envelope(mdt_type t, mdt_count *num_integers, mdt_count *num_addresses,
+                                  mdt_count *num_datatypes, int *combiner);
+MDT_API int mdt_type_get_contents(mdt_type t, mdt_count max_integers, mdt_count max_addresses,
+                                  mdt_count max_datatypes, mdt_count integers[], mdt_aint addresses[],
+                                  mdt_type datatypes[]);
+
 /* Commit (worked example: committed before it is queried): compiles the
  * layout program and uploads its tables to the current HIP device, where
  * they stay resident until the last reference is freed.  Committing twice

@@ -116,6 +116,12 @@ struct TypeNode {
     int nd = 0, order = 0;
     std::vector<int64_t> sizes, subs, starts;
     int64_t rlb = 0, rext = 0;
+    // the constructor call as made (type envelope and contents): combiner,
+    // integer and address arguments, and the child types, which this
+    // node's own children keep alive
+    int combiner = 0;
+    std::vector<int64_t> c_ints, c_addrs;
+    std::vector<TypeNode *> c_types;
     // attributes
     int64_t size = 0, lb = 0, ub = 0, tlb = 0, tub = 0, align = 1;
     bool expl = false;

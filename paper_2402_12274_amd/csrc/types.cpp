@@ -152,6 +152,43 @@ void release(TypeNode *t)
 
 using namespace mdt;
 
+// Record the constructor call (type envelope and contents) on the type it
+// returned.
+static int record(int rc, mdt_type *out, int combiner, std::vector<int64_t> ints, std::vector<int64_t> addrs,
+                  std::vector<mdt_type> types)
+{
+    if (rc != MDT_SUCCESS) return rc;
+    TypeNode *t = as_node(*out);
+    try {
+        t->combiner = combiner;
+        t->c_ints = std::move(ints);
+        t->c_addrs = std::move(addrs);
+        t->c_types.clear();
+        for (mdt_type x : types) t->c_types.push_back(as_node(x));
+    } catch (...) {
+        mdt_type_free(out);
+        return MDT_ERR_NO_MEM;
+    }
+    return rc;
+}
+
+static std::vector<int64_t> cat(std::vector<int64_t> a, const int64_t *b, int64_t n)
+{
+    if (n > 0 && b) a.insert(a.end(), b, b + n);
+    return a;
+}
+
+static std::vector<int64_t> darray_ints(int size, int rank, int nd, const int64_t *gsizes, const int *distribs,
+                                        const int *dargs, const int *psizes, int order)
+{
+    std::vector<int64_t> v = cat({size, rank, nd}, gsizes, nd);
+    for (int k = 0; k < nd; k++) v.push_back(distribs[k]);
+    for (int k = 0; k < nd; k++) v.push_back(dargs[k]);
+    for (int k = 0; k < nd; k++) v.push_back(psizes[k]);
+    v.push_back(order);
+    return v;
+}
+
 #define CHECK_TYPE(t)                                         \
     do {                                                      \
         if (!valid_type(reinterpret_cast<TypeNode *>(t))) return MDT_ERR_TYPE; \
@@ -181,7 +218,7 @@ MDT_API int mdt_type_contiguous(mdt_count n, mdt_type old, mdt_type *out)
         if (!lin_range(n, c->extent(), &lo, &hi)) A.ovf = true;
         else A.add(c, lo, hi, n);
     }
-    return done(t, A, out);
+    return record(done(t, A, out), out, MDT_COMBINER_CONTIGUOUS, {n}, {}, {old});
 }
 
 static int make_hvec(Kind k, int64_t n, int64_t bl, int64_t stride_bytes, int64_t stride_elems, TypeNode *c,
@@ -219,7 +256,8 @@ MDT_API int mdt_type_vector(mdt_count n, mdt_count bl, mdt_count stride, mdt_typ
 {
     CHECK_TYPE(old);
     if (!out || n < 0 || bl < 0) return MDT_ERR_ARG;
-    return make_hvec(K_VECTOR, n, bl, 0, stride, as_node(old), out);
+    return record(make_hvec(K_VECTOR, n, bl, 0, stride, as_node(old), out), out, MDT_COMBINER_VECTOR, {n, bl, stride},
+                  {}, {old});
 }
 
 MDT_API int mdt_type_create_hvector(mdt_count n, mdt_count bl, mdt_aint stride_bytes, mdt_type old,
@@ -227,7 +265,8 @@ MDT_API int mdt_type_create_hvector(mdt_count n, mdt_count bl, mdt_aint stride_b
 {
     CHECK_TYPE(old);
     if (!out || n < 0 || bl < 0) return MDT_ERR_ARG;
-    return make_hvec(K_HVECTOR, n, bl, stride_bytes, 0, as_node(old), out);
+    return record(make_hvec(K_HVECTOR, n, bl, stride_bytes, 0, as_node(old), out), out, MDT_COMBINER_HVECTOR, {n, bl},
+                  {stride_bytes}, {old});
 }
 
 // indexed family: block i holds bl[i] copies starting at disp[i] (elements
@@ -283,7 +322,8 @@ MDT_API int mdt_type_indexed(mdt_count n, const mdt_count bl[], const mdt_count 
 {
     CHECK_TYPE(old);
     if (n > 0 && !bl) return MDT_ERR_ARG;
-    return make_idx(K_INDEXED, n, bl, 0, disp, true, as_node(old), out);
+    return record(make_idx(K_INDEXED, n, bl, 0, disp, true, as_node(old), out), out, MDT_COMBINER_INDEXED,
+                  cat(cat({n}, bl, n), disp, n), {}, {old});
 }
 
 MDT_API int mdt_type_create_hindexed(mdt_count n, const mdt_count bl[], const mdt_aint disp[], mdt_type old,
@@ -291,21 +331,24 @@ MDT_API int mdt_type_create_hindexed(mdt_count n, const mdt_count bl[], const md
 {
     CHECK_TYPE(old);
     if (n > 0 && !bl) return MDT_ERR_ARG;
-    return make_idx(K_HINDEXED, n, bl, 0, disp, false, as_node(old), out);
+    return record(make_idx(K_HINDEXED, n, bl, 0, disp, false, as_node(old), out), out, MDT_COMBINER_HINDEXED,
+                  cat({n}, bl, n), cat({}, disp, n), {old});
 }
 
 MDT_API int mdt_type_create_indexed_block(mdt_count n, mdt_count bl, const mdt_count disp[], mdt_type old,
                                           mdt_type *out)
 {
     CHECK_TYPE(old);
-    return make_idx(K_INDEXED, n, nullptr, bl, disp, true, as_node(old), out);
+    return record(make_idx(K_INDEXED, n, nullptr, bl, disp, true, as_node(old), out), out,
+                  MDT_COMBINER_INDEXED_BLOCK, cat({n, bl}, disp, n), {}, {old});
 }
 
 MDT_API int mdt_type_create_hindexed_block(mdt_count n, mdt_count bl, const mdt_aint disp[], mdt_type old,
                                            mdt_type *out)
 {
     CHECK_TYPE(old);
-    return make_idx(K_HINDEXED, n, nullptr, bl, disp, false, as_node(old), out);
+    return record(make_idx(K_HINDEXED, n, nullptr, bl, disp, false, as_node(old), out), out,
+                  MDT_COMBINER_HINDEXED_BLOCK, {n, bl}, cat({}, disp, n), {old});
 }
 
 MDT_API int mdt_type_create_struct(mdt_count n, const mdt_count bl[], const mdt_aint disp[],
@@ -339,7 +382,8 @@ MDT_API int mdt_type_create_struct(mdt_count n, const mdt_count bl[], const mdt_
         }
         A.add(c, lo, hi, bl[i]);
     }
-    return done(t, A, out);
+    return record(done(t, A, out), out, MDT_COMBINER_STRUCT, cat({n}, bl, n), cat({}, disp, n),
+                  std::vector<mdt_type>(types, types + n));
 }
 
 MDT_API int mdt_type_create_subarray(int ndims, const mdt_count sizes[], const mdt_count subsizes[],
@@ -393,7 +437,9 @@ MDT_API int mdt_type_create_subarray(int ndims, const mdt_count sizes[], const m
         A.ub = ub;
         A.expl = true;
     }
-    return done(t, A, out);
+    std::vector<int64_t> ci = cat(cat(cat({ndims}, sizes, ndims), subsizes, ndims), starts, ndims);
+    ci.push_back(order);
+    return record(done(t, A, out), out, MDT_COMBINER_SUBARRAY, std::move(ci), {}, {old});
 }
 
 MDT_API int mdt_type_create_resized(mdt_type old, mdt_aint lb, mdt_aint extent, mdt_type *out)
@@ -415,7 +461,7 @@ MDT_API int mdt_type_create_resized(mdt_type old, mdt_aint lb, mdt_aint extent, 
     A.ub = ub;
     A.placed = true;
     A.expl = true;
-    return done(t, A, out);
+    return record(done(t, A, out), out, MDT_COMBINER_RESIZED, {}, {lb, extent}, {old});
 }
 
 MDT_API int mdt_type_dup(mdt_type old, mdt_type *out)
@@ -438,7 +484,7 @@ MDT_API int mdt_type_dup(mdt_type old, mdt_type *out)
         d->lb = c->lb;
         d->ub = c->ub;
     }
-    return rc;
+    return record(rc, out, MDT_COMBINER_DUP, {}, {}, {old});
 }
 
 // Distributed array: the indices each dimension owns are a list of blocks
@@ -500,7 +546,9 @@ MDT_API int mdt_type_create_darray(int size, int rank, int ndims, const mdt_coun
             sub[k] = blocks[k].empty() ? 0 : blocks[k][0].second;
             st[k] = blocks[k].empty() ? 0 : blocks[k][0].first;
         }
-        return mdt_type_create_subarray(ndims, gsizes, sub.data(), st.data(), order, old, out);
+        return record(mdt_type_create_subarray(ndims, gsizes, sub.data(), st.data(), order, old, out), out,
+                      MDT_COMBINER_DARRAY, darray_ints(size, rank, ndims, gsizes, distribs, dargs, psizes, order), {},
+                      {old});
     }
     // fastest dimension first; cur holds a reference the loop owns (old is
     // borrowed until the first step replaces it).  A dimension's full
@@ -556,6 +604,39 @@ MDT_API int mdt_type_create_darray(int size, int rank, int ndims, const mdt_coun
         return rc;
     }
     *out = cur;
+    return record(MDT_SUCCESS, out, MDT_COMBINER_DARRAY,
+                  darray_ints(size, rank, ndims, gsizes, distribs, dargs, psizes, order), {}, {old});
+}
+
+MDT_API int mdt_type_get_envelope(mdt_type t, mdt_count *num_integers, mdt_count *num_addresses,
+                                  mdt_count *num_datatypes, int *combiner)
+{
+    CHECK_TYPE(t);
+    if (!num_integers || !num_addresses || !num_datatypes || !combiner) return MDT_ERR_ARG;
+    const TypeNode *n = as_node(t);
+    *num_integers = (mdt_count)n->c_ints.size();
+    *num_addresses = (mdt_count)n->c_addrs.size();
+    *num_datatypes = (mdt_count)n->c_types.size();
+    *combiner = n->predefined ? MDT_COMBINER_NAMED : n->combiner;
+    return MDT_SUCCESS;
+}
+
+MDT_API int mdt_type_get_contents(mdt_type t, mdt_count max_integers, mdt_count max_addresses,
+                                  mdt_count max_datatypes, mdt_count integers[], mdt_aint addresses[],
+                                  mdt_type datatypes[])
+{
+    CHECK_TYPE(t);
+    const TypeNode *n = as_node(t);
+    const int64_t ni = (int64_t)n->c_ints.size(), na = (int64_t)n->c_addrs.size(), nt = (int64_t)n->c_types.size();
+    if (n->predefined || max_integers < ni || max_addresses < na || max_datatypes < nt) return MDT_ERR_ARG;
+    if ((ni && !integers) || (na && !addresses) || (nt && !datatypes)) return MDT_ERR_ARG;
+    std::copy(n->c_ints.begin(), n->c_ints.end(), integers);
+    std::copy(n->c_addrs.begin(), n->c_addrs.end(), addresses);
+    for (int64_t i = 0; i < nt; i++) {
+        TypeNode *c = n->c_types[(size_t)i];
+        if (!c->predefined) retain(c);
+        datatypes[i] = reinterpret_cast<mdt_type>(c);
+    }
     return MDT_SUCCESS;
 }
 

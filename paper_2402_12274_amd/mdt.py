@@ -97,6 +97,8 @@ _SIGS = {
     "mdt_type_create_subarray": ([_INT, _I64P, _I64P, _I64P, _INT, _P, C.POINTER(_P)], _INT),
     "mdt_type_create_darray": ([_INT, _INT, _INT, _I64P, C.POINTER(_INT), C.POINTER(_INT), C.POINTER(_INT), _INT, _P,
                                 C.POINTER(_P)], _INT),
+    "mdt_type_get_envelope": ([_P, _I64P, _I64P, _I64P, C.POINTER(_INT)], _INT),
+    "mdt_type_get_contents": ([_P, _I64, _I64, _I64, _I64P, _I64P, C.POINTER(_P)], _INT),
     "mdt_type_create_resized": ([_P, _I64, _I64, C.POINTER(_P)], _INT),
     "mdt_type_dup": ([_P, C.POINTER(_P)], _INT),
     "mdt_type_commit": ([C.POINTER(_P)], _INT),
@@ -258,6 +260,69 @@ def _new(fn, *args, what="constructor") -> Type:
     out = _P()
     check(fn(*args, C.byref(out)), what)
     return Type(out.value)
+
+
+COMBINERS = ("named", "dup", "contiguous", "vector", "hvector", "indexed", "hindexed", "indexed_block",
+             "hindexed_block", "struct", "subarray", "darray", "resized")
+
+
+def envelope(t: Type):
+    """(combiner name, number of integers, addresses, datatypes)."""
+    ni, na, nt, comb = C.c_int64(), C.c_int64(), C.c_int64(), _INT()
+    check(_lib.mdt_type_get_envelope(t.h, C.byref(ni), C.byref(na), C.byref(nt), C.byref(comb)), "get_envelope")
+    return COMBINERS[comb.value], ni.value, na.value, nt.value
+
+
+def spec_of(t: Type):
+    """The constructor spec a type was built from, read back through its
+    envelope and contents (recursively): build_type(spec_of(t)) rebuilds it."""
+    comb, ni, na, nt = envelope(t)
+    if comb == "named":
+        names = {_lib.mdt_basic(code): name for name, code in BASIC_CODES.items()}
+        return ("basic", names[t.h.value])
+    ints = np.zeros(max(ni, 1), np.int64)
+    addrs = np.zeros(max(na, 1), np.int64)
+    kids = (_P * max(nt, 1))()
+    check(_lib.mdt_type_get_contents(t.h, ni, na, nt, ints.ctypes.data_as(_I64P), addrs.ctypes.data_as(_I64P), kids),
+          "get_contents")
+    iv = [int(x) for x in ints[:ni]]
+    av = [int(x) for x in addrs[:na]]
+    # derived children come back as new references (freed when the wrapper
+    # goes); predefined ones as themselves (freeing those is a no-op error)
+    ch = [spec_of(Type(kids[i])) for i in range(nt)]
+    order = {ORDER_C: "C", ORDER_FORTRAN: "F"}
+    if comb == "dup":
+        return ("dup", ch[0])
+    if comb == "contiguous":
+        return ("contiguous", iv[0], ch[0])
+    if comb == "vector":
+        return ("vector", iv[0], iv[1], iv[2], ch[0])
+    if comb == "hvector":
+        return ("hvector", iv[0], iv[1], av[0], ch[0])
+    if comb == "indexed":
+        n = iv[0]
+        return ("indexed", iv[1:1 + n], iv[1 + n:1 + 2 * n], ch[0])
+    if comb == "hindexed":
+        return ("hindexed", iv[1:], av, ch[0])
+    if comb == "indexed_block":
+        return ("indexed_block", iv[1], iv[2:], ch[0])
+    if comb == "hindexed_block":
+        return ("hindexed_block", iv[1], av, ch[0])
+    if comb == "struct":
+        return ("struct", iv[1:], av, ch)
+    if comb == "subarray":
+        nd = iv[0]
+        return ("subarray", iv[1:1 + nd], iv[1 + nd:1 + 2 * nd], iv[1 + 2 * nd:1 + 3 * nd], order[iv[-1]], ch[0])
+    if comb == "darray":
+        size, rank, nd = iv[0], iv[1], iv[2]
+        g = iv[3:3 + nd]
+        dist = [{DISTRIBUTE_NONE: "none", DISTRIBUTE_BLOCK: "block", DISTRIBUTE_CYCLIC: "cyclic"}[d]
+                for d in iv[3 + nd:3 + 2 * nd]]
+        darg = [None if a == DISTRIBUTE_DFLT_DARG else a for a in iv[3 + 2 * nd:3 + 3 * nd]]
+        return ("darray", size, rank, g, dist, darg, iv[3 + 3 * nd:3 + 4 * nd], order[iv[-1]], ch[0])
+    if comb == "resized":
+        return ("resized", av[0], av[1], ch[0])
+    raise ValueError(comb)
 
 
 def build_type(spec, commit: bool = True) -> Type:

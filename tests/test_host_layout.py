@@ -192,3 +192,52 @@ def test_darray_errors():
         with pytest.raises(mdt.MdtError) as e:
             mdt.build_type(spec)
         assert e.value.code == mdt.ERR_ARG, spec
+
+
+def _norm(spec):
+    """A spec with every array as a plain list of ints (for comparison)."""
+    if isinstance(spec, tuple):
+        return tuple(_norm(x) for x in spec)
+    if isinstance(spec, (list, np.ndarray)):
+        return [_norm(x) for x in list(spec)]
+    if isinstance(spec, (np.integer,)):
+        return int(spec)
+    return spec
+
+
+def test_envelope_and_contents_round_trip():
+    """Type envelope and contents give back the constructor call each type
+    was made with, recursively, for every constructor (random tiny types,
+    distributed arrays, the workload types); the rebuilt type has the same
+    attributes and segments."""
+    from typegen import darray_specs
+
+    specs = list(SPECS[:120]) + darray_specs(5, 40) + [inputs.vector_small(), inputs.particle_struct()]
+    specs += [s for _, s in inputs.halo_faces(64)]
+    specs += [("indexed_block", 3, [4, 0, 9], ("basic", "INT16")), ("hindexed_block", 2, [16, -8], ("basic", "INT32")),
+              ("dup", ("vector", 3, 2, 4, ("basic", "DOUBLE")))]
+    for spec in specs:
+        t = mdt.build_type(spec)
+        back = mdt.spec_of(t)
+        assert _norm(back) == _norm(spec), (spec, back)
+        t2 = mdt.build_type(back)
+        assert t2.size() == t.size() and t2.extent() == t.extent() and t2.true_extent() == t.true_extent()
+        n = t.iov_len(-1)[0]
+        b1, l1 = t.iov(0, n)
+        b2, l2 = t2.iov(0, n)
+        assert np.array_equal(b1, b2) and np.array_equal(l1, l2)
+
+
+def test_envelope_of_predefined_and_errors():
+    import ctypes as C
+
+    comb, ni, na, nt = mdt.envelope(mdt.Type(mdt.lib().mdt_basic(mdt.BASIC_CODES["DOUBLE"]), owned=False))
+    assert (comb, ni, na, nt) == ("named", 0, 0, 0)
+    t = mdt.build_type(("vector", 3, 2, 4, ("basic", "DOUBLE")))
+    ints = (C.c_int64 * 3)()
+    kids = (C.c_void_p * 1)()
+    # too small an integer array: nothing written
+    assert mdt.lib().mdt_type_get_contents(t.h, 2, 0, 1, ints, None, kids) == mdt.ERR_ARG
+    assert list(ints) == [0, 0, 0] and kids[0] is None
+    d = mdt.Type(mdt.lib().mdt_basic(mdt.BASIC_CODES["DOUBLE"]), owned=False)
+    assert mdt.lib().mdt_type_get_contents(d.h, 0, 0, 0, None, None, None) == mdt.ERR_ARG
