@@ -49,7 +49,7 @@ TRAFFIC_TABLE = os.path.join(HERE, "profiles", "hbm_traffic.md")
 # the sources that decide what the kernels execute: kernel bodies, the
 # layout program and its tables, launch selection and the batch kernels
 KERNEL_SOURCES = ("batch.hip", "batch_kernel.h", "batch_p0u0.hip", "batch_p0u1.hip", "batch_p1u0.hip",
-                  "batch_p1u1.hip", "compile.cpp", "device.h", "device.hip", "layout_dev.h", "xfer.h")
+                  "batch_p1u1.hip", "batch_p2u0.hip", "batch_p2u1.hip", "compile.cpp", "device.h", "device.hip", "layout_dev.h", "xfer.h")
 
 
 def kernel_sources_sha():

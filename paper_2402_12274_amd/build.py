@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libmdt.so")
 LOADGEN = os.path.join(HERE, "libmdt_loadgen.so")
 
 SOURCES = ["types.cpp", "compile.cpp", "api.cpp", "requests.cpp", "device.hip", "batch.hip", "batch_p0u0.hip", "batch_p0u1.hip",
-           "batch_p1u0.hip", "batch_p1u1.hip", "server.cpp"]
+           "batch_p1u0.hip", "batch_p1u1.hip", "batch_p2u0.hip", "batch_p2u1.hip", "server.cpp"]
 ARCH = os.environ.get("MDT_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall", "-Wno-unused-function",

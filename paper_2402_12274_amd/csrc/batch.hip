@@ -204,7 +204,7 @@ int build_order(mdt_batch_s *b, const ReqDesc *D, const int64_t *tile0, const Ba
                          });
         const int64_t n = (int64_t)keys.size();
         int64_t nslots = n;
-        if (b->cfg.policy == 0 && n > 0) {
+        if (b->cfg.policy != 1 && n > 0) {
             // groups g = 0, 1, ... of XCD_GROUP sorted tiles; group g runs on
             // XCD g mod XCDS.  Slot t (XCD t mod XCDS, i-th slot of that XCD)
             // takes position p of group (i / XCD_GROUP) * XCDS + XCD.
@@ -321,6 +321,12 @@ void enqueue_kernels(mdt_batch_s *b, hipStream_t s)
             hipLaunchKernelGGL(batch_counter_reset, dim3(1), dim3(1), 0, s, ctr);
             if (dir) launch_dir<1, 1>(b, s, grid, lds, ctr, body);
             else launch_dir<1, 0>(b, s, grid, lds, ctr, body);
+        } else if (b->cfg.policy == 2 &&
+                   (int64_t)grid.x == (b->cfg.order ? b->nslots_dir[dir] : b->ntiles_dir[dir])) {
+            // one tile (or slot) per workgroup: the loop-free variant (the
+            // looping one below covers a grid too small for that)
+            if (dir) launch_dir<2, 1>(b, s, grid, lds, ctr, body);
+            else launch_dir<2, 0>(b, s, grid, lds, ctr, body);
         } else {
             if (dir) launch_dir<0, 1>(b, s, grid, lds, ctr, body);
             else launch_dir<0, 0>(b, s, grid, lds, ctr, body);
@@ -388,7 +394,8 @@ bool valid_cfg(const mdt_batch_config &c)
 {
     bool tc = c.tile_chunks == 256 || c.tile_chunks == 512 || c.tile_chunks == 1024 || c.tile_chunks == 2048 ||
               c.tile_chunks == 4096;
-    return tc && c.wgs_per_cu >= 0 && c.wgs_per_cu <= 16 && (c.policy == 0 || c.policy == 1) &&
+    return tc && c.wgs_per_cu >= 0 && c.wgs_per_cu <= 16 && c.policy >= 0 && c.policy <= 2 &&
+           (c.policy != 2 || c.wgs_per_cu == 0) &&
            (c.use_graph == 0 || c.use_graph == 1) && (c.order == 0 || c.order == 1);
 }
 
@@ -609,10 +616,11 @@ MDT_API int mdt_batch_autotune(mdt_batch b, mdt_stream s, mdt_batch_config *best
     int rc = MDT_SUCCESS;
     for (int graph = 0; graph < 2 && !rc; graph++)
         for (int ord = 0; ord < 2 && !rc; ord++)
-            for (int policy = 0; policy < 2 && !rc; policy++)
+            for (int policy = 0; policy < 3 && !rc; policy++)
                 for (int tc : tiles)
                     for (int w : occ) {
                         if (policy == 1 && w == 0) continue;  // nothing to balance with a workgroup per tile
+                        if (policy == 2 && w != 0) continue;  // the loop-free kernel takes one tile per workgroup
                         mdt_batch_config c{tc, w, policy, graph, ord};
                         mdt_batch_set_config(b, &c);
                         rc = launch(b, s->s);  // warm-up (uploads, graph capture)

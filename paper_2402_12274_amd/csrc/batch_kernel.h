@@ -131,8 +131,9 @@ __device__ __forceinline__ const DevLayout &const_layout(uint64_t addr)
 }
 
 // Batch kernel for one direction.  POLICY 0: tile t = blockIdx.x + k *
-// gridDim.x (with one workgroup per tile, each workgroup takes one tile);
-// POLICY 1: tiles taken from an atomic counter.  Every workgroup leaves the
+// gridDim.x; POLICY 1: tiles taken from an atomic counter; POLICY 2: one
+// tile (or order-table slot) per workgroup, with no loop, so no loop state
+// holds scalar registers the tile bodies need.  Every workgroup leaves the
 // loop once the tile index passes the direction's last tile.
 template <int POLICY, int UNPACK, int BODY>
 __global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restrict__ H,
@@ -151,7 +152,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restric
     const int64_t t_begin = ordered ? (UNPACK ? H->nslots_dir[0] : 0) : (UNPACK ? H->ntiles_dir[0] : 0);
     const int64_t t_end = t_begin + (ordered ? H->nslots_dir[UNPACK] : H->ntiles_dir[UNPACK]);
     int64_t t;
-    if (POLICY == 0) {
+    if (POLICY != 1) {
         t = t_begin + blockIdx.x;
     } else {
         if (threadIdx.x == 0) s_t = t_begin + (int64_t)atomicAdd(counter, 1ull);
@@ -182,6 +183,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restric
             int64_t cend = c0 + T < D.nchunks ? c0 + T : D.nchunks;
             run_tile<UNPACK, BODY>(L, A, D.body, D.kind, c0, cend, lds_dyn, D);
         }
+        if (POLICY == 2) break;
         if (POLICY == 0) {
             t += gridDim.x;
         } else {
@@ -210,6 +212,8 @@ MDT_BATCH_DIR(0, 0)
 MDT_BATCH_DIR(0, 1)
 MDT_BATCH_DIR(1, 0)
 MDT_BATCH_DIR(1, 1)
+MDT_BATCH_DIR(2, 0)
+MDT_BATCH_DIR(2, 1)
 #undef MDT_BATCH_DIR
 
 // one direction: a kernel with only the body the direction needs, else one

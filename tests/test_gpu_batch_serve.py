@@ -113,7 +113,7 @@ def test_batch_equals_alone(env):
     b = mdt.Batch()
     for (t, src, n), o in zip(plan, offs):
         assert b.add_pack(src.data_ptr(), 1, t, 0, out.data_ptr() + int(o) + 3, n) == n
-    for policy, wgs, order in ((0, 4, 0), (1, 4, 0), (0, 0, 0), (0, 4, 1), (1, 2, 1), (0, 0, 1)):
+    for policy, wgs, order in ((0, 4, 0), (1, 4, 0), (0, 0, 0), (0, 4, 1), (1, 2, 1), (0, 0, 1), (2, 0, 0), (2, 0, 1)):
         for graph in (1, 0):
             for tc in (256, 4096):
                 note(f"batch policy={policy} wgs={wgs} order={order} graph={graph} tile={tc}")
@@ -177,8 +177,8 @@ def test_batch_mixed_directions(env):
         dexp.append(e)
         dsts.append(to_dev(canary))
     ms = mdt.Stream(torch.cuda.current_stream().cuda_stream)
-    for wgs, order in ((0, 0), (2, 0), (0, 1), (4, 1)):
-        note(f"mixed-direction batch wgs={wgs} order={order}")
+    for wgs, order, pol in ((0, 0, 0), (2, 0, 0), (0, 1, 0), (4, 1, 0), (0, 0, 2), (0, 1, 2)):
+        note(f"mixed-direction batch wgs={wgs} order={order} policy={pol}")
         for d, o in zip(dsts, orc):
             d.fill_(0x33)
         for x in outs:
@@ -187,7 +187,7 @@ def test_batch_mixed_directions(env):
         for i, (t, c) in enumerate(zip(types, counts)):
             b.add_unpack(pks[i].data_ptr(), exps[i].size, dsts[i].data_ptr(), c, t, 0)
             b.add_pack(srcs[i].data_ptr(), c, t, 0, outs[i].data_ptr(), -1)
-        b.set_config(mdt.BatchConfig(1024, wgs, 0, 1, order))
+        b.set_config(mdt.BatchConfig(1024, wgs, pol, 1, order))
         b.launch(ms)
         torch.cuda.synchronize()
         for i in range(len(specs)):
@@ -213,8 +213,8 @@ def test_batch_single_body_kernels(env):
         types = [mdt.build_type(sp) for sp in specs]
         kind, rec = expect_body[name]
         assert all(t.layout_info()["kind"] == kind and t.layout_info()["records"] == rec for t in types), name
-        for wgs, order in ((0, 0), (4, 1)):
-            note(f"single-body batch {name} wgs={wgs} order={order}")
+        for wgs, order, pol in ((0, 0, 0), (4, 1, 0), (0, 0, 2)):
+            note(f"single-body batch {name} wgs={wgs} order={order} policy={pol}")
             bp, bu = mdt.Batch(), mdt.Batch()
             keep = []
             for i, (sp, t) in enumerate(zip(specs, types)):
@@ -233,7 +233,7 @@ def test_batch_single_body_kernels(env):
                 bu.add_unpack(pk.data_ptr(), full.size, dst.data_ptr(), c, t, 0)
                 keep.append((src, out, full, pk, dst, exp_u))
             for b in (bp, bu):
-                b.set_config(mdt.BatchConfig(1024, wgs, 0, 1, order))
+                b.set_config(mdt.BatchConfig(1024, wgs, pol, 1, order))
                 b.launch(ms)
             torch.cuda.synchronize()
             for src, out, full, pk, dst, exp_u in keep:

@@ -208,8 +208,8 @@ def test_copy_requests_in_a_batch():
     rh = inputs.random_bytes(5000 * 40, seed=52)
     rexp_pack = obuild(rec).pack(rh, 0, 5000)
     ms = mdt.Stream(torch.cuda.current_stream().cuda_stream)
-    for wgs, order in ((0, 0), (4, 1)):
-        note(f"batch with copies wgs={wgs} order={order}")
+    for wgs, order, pol in ((0, 0, 0), (4, 1, 0), (0, 0, 2)):
+        note(f"batch with copies wgs={wgs} order={order} policy={pol}")
         arr = to_dev(host)
         rsrc = to_dev(rh)
         rout = torch.zeros(rexp_pack.size, dtype=torch.uint8, device="cuda")
@@ -221,7 +221,7 @@ def test_copy_requests_in_a_batch():
             b.add_copy(arr.data_ptr(), 1, mdt.build_type(sa), arr.data_ptr(), 1, mdt.build_type(sb), 0, -1)
         pk = to_dev(rexp_pack)
         b.add_unpack(pk.data_ptr(), rexp_pack.size, rback.data_ptr(), 5000, tr, 0)
-        b.set_config(mdt.BatchConfig(1024, wgs, 0, 1, order))
+        b.set_config(mdt.BatchConfig(1024, wgs, pol, 1, order))
         b.launch(ms)
         torch.cuda.synchronize()
         assert first_diff(to_host(arr), exp) is None
