@@ -106,6 +106,11 @@ struct Item {
     double t_submit = 0, t_launch = 0, t_done = 0;
     std::atomic<int> state{0};  // 0 queued, 1 admitted, 2 launched, 3 done
     bool deferred = false;
+    // the launch holding the item (set before state becomes 2): its stream,
+    // slot and launch number on that stream
+    struct StreamState *st = nullptr;
+    struct Slot *slot = nullptr;
+    uint64_t seq = 0;
 };
 
 // Allocator over one device allocation: free ranges indexed by offset (for
@@ -450,11 +455,14 @@ int progress_locked(mdt_server s)
                 rc = r ? r : MDT_ERR_HIP;
                 continue;
             }
-            it->state.store(2, std::memory_order_release);
-            it->t_launch = now_us();
             sl->items.push_back(it);
             sl->busy = true;
             sl->seq = best->next_seq++;
+            it->st = best;
+            it->slot = sl;
+            it->seq = sl->seq;
+            it->t_launch = now_us();
+            it->state.store(2, std::memory_order_release);
             sl->bytes = it->nbytes;
             best->busy++;
             best->bytes += sl->bytes;
@@ -481,7 +489,6 @@ int progress_locked(mdt_server s)
                 complete(s, it, r, now_us());
                 continue;
             }
-            it->state.store(2, std::memory_order_release);
             sl->items.push_back(it);
             n++;
         }
@@ -503,6 +510,12 @@ int progress_locked(mdt_server s)
         sl->bytes = bytes;
         best->busy++;
         best->bytes += bytes;
+        for (Item *it : sl->items) {
+            it->st = best;
+            it->slot = sl;
+            it->seq = sl->seq;
+            it->state.store(2, std::memory_order_release);
+        }
         s->launches++;
         s->launches_inflight.fetch_add(1, std::memory_order_relaxed);
     }
@@ -583,24 +596,32 @@ int submit(mdt_server s, Item *it, mdt_request *req)
     r->kind = REQ_SERVER;
     r->server_item = it;
     it->t_submit = now_us();
-    {
+    // While a launch slot is free and nothing else waits (or without a
+    // progress thread) the submitter runs a progress round itself, so its
+    // request is admitted and launched now; it takes the progress lock
+    // before queuing, so the progress thread does not race it for the same
+    // request.  Once the slots are full or requests queue, it only queues:
+    // the progress thread cuts whatever has queued into batched launches,
+    // which keeps the cost per submit low and the launches few.
+    const bool thread = s->run_thread.load(std::memory_order_acquire);
+    const int nl = s->launches_inflight.load(std::memory_order_relaxed);
+    const bool waiting = s->work.load(std::memory_order_acquire) > (int64_t)nl;
+    auto enqueue = [&] {
         std::lock_guard<std::mutex> q(s->qmu);
         s->submitted++;
         if (s->first_submit < 0) s->first_submit = it->t_submit;
         s->queue.push_back(it);
         s->work.fetch_add(1, std::memory_order_release);  // under qmu: a sleeping thread sees it
+    };
+    if (!thread || (nl < (int)s->streams.size() * s->cfg.max_inflight && !waiting)) {
+        std::lock_guard<std::mutex> g(s->mu);
+        enqueue();
+        if (!thread) reap_locked(s);
+        progress_locked(s);
+    } else {
+        enqueue();
+        s->wake.notify_one();
     }
-    // While a launch slot is free and nothing else waits (or without a
-    // progress thread) the submitter runs a progress round itself, so its
-    // request is admitted and launched now.  Once the slots are full or
-    // requests queue, it only queues: the progress thread cuts whatever has
-    // queued into batched launches, which keeps the cost per submit low and
-    // the launches few.
-    const bool thread = s->run_thread.load(std::memory_order_acquire);
-    const int nl = s->launches_inflight.load(std::memory_order_relaxed);
-    const bool waiting = s->work.load(std::memory_order_acquire) > (int64_t)nl + 1;  // besides this request
-    if (!thread || (nl < (int)s->streams.size() * s->cfg.max_inflight && !waiting)) progress(s);
-    s->wake.notify_one();
     *req = r;
     return MDT_SUCCESS;
 }
@@ -757,7 +778,29 @@ MDT_API int mdt_server_request_test(mdt_server srv, mdt_request req, int *flag)
 {
     Item *it = item_of(req);
     if (!valid_server(srv) || !it || !flag) return MDT_ERR_ARG;
-    if (it->state.load(std::memory_order_acquire) != 3) {
+    const int st = it->state.load(std::memory_order_acquire);
+    if (st == 2 && srv->run_thread.load()) {
+        // the client queries the event of its own launch only (as the caller
+        // of a plain enqueue queries its own event); once it has finished,
+        // that launch and the earlier ones on its stream (a stream finishes
+        // in order) are retired and waiting requests launched
+        Slot *sl = it->slot;
+        StreamState *ss = it->st;
+        const uint64_t seq = it->seq;
+        if (hipEventQuery(sl->ev) != hipErrorNotReady) {
+            std::lock_guard<std::mutex> g(srv->mu);
+            if (sl->busy && sl->seq == seq) {
+                for (;;) {
+                    Slot *old = oldest_busy(*ss);
+                    if (!old || old->seq > seq) break;
+                    hipError_t e = hipEventQuery(old->ev);
+                    if (e == hipErrorNotReady) break;  // cannot happen on an in-order stream; keep it queued
+                    retire(srv, *ss, *old, e);
+                }
+                progress_locked(srv);
+            }
+        }
+    } else if (st != 3) {
         if (!srv->run_thread.load()) {
             progress(srv);
         } else if (now_us() - srv->last_reap.load(std::memory_order_relaxed) >= TEST_REAP_US && srv->mu.try_lock()) {
