@@ -511,40 +511,48 @@ MDT_API int mdt_type_create_darray(int size, int rank, int ndims, const mdt_coun
         coord[k] = r % psizes[k];
         r /= psizes[k];
     }
-    // owned blocks (start, length) of every dimension, in increasing order
-    std::vector<std::vector<std::pair<int64_t, int64_t>>> blocks(ndims);
+    // owned indices of every dimension as equally spaced blocks: `count`
+    // blocks of `len` indices, the first at `first`, `step` apart, the last
+    // one `last` long (0 blocks when the coordinate owns nothing)
+    struct Blocks {
+        int64_t first = 0, len = 0, step = 0, count = 0, last = 0;
+    };
+    std::vector<Blocks> blocks(ndims);
     bool single = true;
     for (int k = 0; k < ndims; k++) {
         const int64_t g = gsizes[k], P = psizes[k], c = coord[k];
         const int d = dargs[k];
+        Blocks &B = blocks[k];
         if (d != MDT_DISTRIBUTE_DFLT_DARG && d < 1) return MDT_ERR_ARG;
-        if (distribs[k] == MDT_DISTRIBUTE_NONE) {
-            if (P != 1) return MDT_ERR_ARG;
-            blocks[k].push_back({0, g});
+        if (distribs[k] == MDT_DISTRIBUTE_NONE || (distribs[k] == MDT_DISTRIBUTE_CYCLIC && P == 1)) {
+            if (distribs[k] == MDT_DISTRIBUTE_NONE && P != 1) return MDT_ERR_ARG;
+            B = {0, g, g, 1, g};  // the whole dimension
         } else if (distribs[k] == MDT_DISTRIBUTE_BLOCK) {
             const int64_t b = d == MDT_DISTRIBUTE_DFLT_DARG ? (g + P - 1) / P : d;
             int64_t cover;
             if (!mul_ok(b, P, &cover) || cover < g) return MDT_ERR_ARG;
             const int64_t st = c * b;
-            if (st < g) blocks[k].push_back({st, std::min(b, g - st)});
+            if (st < g) B = {st, std::min(b, g - st), b, 1, std::min(b, g - st)};
         } else if (distribs[k] == MDT_DISTRIBUTE_CYCLIC) {
             const int64_t b = d == MDT_DISTRIBUTE_DFLT_DARG ? 1 : d;
-            int64_t step;
-            if (!mul_ok(b, P, &step)) return MDT_ERR_ARG;
-            for (int64_t st = c * b; st < g; st += step) {
-                blocks[k].push_back({st, std::min(b, g - st)});
-                if (g - st <= step) break;
+            int64_t step, first;
+            if (!mul_ok(b, P, &step) || !mul_ok(c, b, &first)) return MDT_ERR_ARG;
+            if (first < g) {
+                const int64_t count = (g - first + step - 1) / step;
+                const int64_t last_start = first + (count - 1) * step;
+                B = {first, b, step, count, std::min(b, g - last_start)};
+                if (count == 1) B.len = B.last;
             }
         } else {
             return MDT_ERR_ARG;
         }
-        single = single && blocks[k].size() <= 1;
+        single = single && B.count <= 1;
     }
     if (single) {
         std::vector<mdt_count> sub(ndims), st(ndims);
         for (int k = 0; k < ndims; k++) {
-            sub[k] = blocks[k].empty() ? 0 : blocks[k][0].second;
-            st[k] = blocks[k].empty() ? 0 : blocks[k][0].first;
+            sub[k] = blocks[k].count ? blocks[k].len : 0;
+            st[k] = blocks[k].count ? blocks[k].first : 0;
         }
         return record(mdt_type_create_subarray(ndims, gsizes, sub.data(), st.data(), order, old, out), out,
                       MDT_COMBINER_DARRAY, darray_ints(size, rank, ndims, gsizes, distribs, dargs, psizes, order), {},
@@ -561,33 +569,29 @@ MDT_API int mdt_type_create_darray(int size, int rank, int ndims, const mdt_coun
     int rc = MDT_SUCCESS;
     for (int i = 0; i < ndims && rc == MDT_SUCCESS; i++) {
         const int k = order == MDT_ORDER_C ? ndims - 1 - i : i;
-        const auto &B = blocks[k];
-        const size_t nb = B.size();
+        const Blocks &B = blocks[k];
         int64_t span;
         if (!mul_ok(gsizes[k], E, &span)) rc = MDT_ERR_ARG;
         mdt_type placed = MDT_TYPE_NULL;  // the dimension's owned blocks of cur, at their displacements
-        if (rc == MDT_SUCCESS && nb <= 1) {
-            mdt_count bl = nb ? B[0].second : 0;
-            mdt_aint disp = 0;
-            if (nb && !mul_ok(B[0].first, E, &disp)) rc = MDT_ERR_ARG;
-            if (rc == MDT_SUCCESS) rc = mdt_type_create_hindexed((mdt_count)nb, &bl, &disp, cur, &placed);
+        int64_t d0 = 0;
+        if (rc == MDT_SUCCESS && !mul_ok(B.first, E, &d0)) rc = MDT_ERR_ARG;
+        if (rc == MDT_SUCCESS && B.count <= 1) {
+            mdt_count bl = B.count ? B.len : 0;
+            rc = mdt_type_create_hindexed(B.count, &bl, &d0, cur, &placed);
         } else if (rc == MDT_SUCCESS) {
-            const int64_t kb = B[0].second;                  // block length
-            const size_t nfull = B.back().second == kb ? nb : nb - 1;
-            int64_t stride, d0;
-            if (!mul_ok(B[1].first - B[0].first, E, &stride) || !mul_ok(B[0].first, E, &d0)) rc = MDT_ERR_ARG;
+            const int64_t nfull = B.last == B.len ? B.count : B.count - 1;
+            int64_t stride, dt;
+            if (!mul_ok(B.step, E, &stride) || !mul_ok(B.first + (B.count - 1) * B.step, E, &dt)) rc = MDT_ERR_ARG;
             mdt_type vec = MDT_TYPE_NULL;
-            if (rc == MDT_SUCCESS) rc = mdt_type_create_hvector((mdt_count)nfull, kb, stride, cur, &vec);
-            if (rc == MDT_SUCCESS && nfull == nb) {
+            if (rc == MDT_SUCCESS) rc = mdt_type_create_hvector(nfull, B.len, stride, cur, &vec);
+            if (rc == MDT_SUCCESS && nfull == B.count) {
                 mdt_count one = 1;
                 rc = mdt_type_create_hindexed(1, &one, &d0, vec, &placed);
             } else if (rc == MDT_SUCCESS) {
-                int64_t dt;
-                if (!mul_ok(B.back().first, E, &dt)) rc = MDT_ERR_ARG;
-                mdt_count bl2[2] = {1, B.back().second};
+                mdt_count bl2[2] = {1, B.last};
                 mdt_aint disp2[2] = {d0, dt};
                 mdt_type kids[2] = {vec, cur};
-                if (rc == MDT_SUCCESS) rc = mdt_type_create_struct(2, bl2, disp2, kids, &placed);
+                rc = mdt_type_create_struct(2, bl2, disp2, kids, &placed);
             }
             if (vec) mdt_type_free(&vec);
         }

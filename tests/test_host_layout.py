@@ -241,3 +241,22 @@ def test_envelope_of_predefined_and_errors():
     assert list(ints) == [0, 0, 0] and kids[0] is None
     d = mdt.Type(mdt.lib().mdt_basic(mdt.BASIC_CODES["DOUBLE"]), owned=False)
     assert mdt.lib().mdt_type_get_contents(d.h, 0, 0, 0, None, None, None) == mdt.ERR_ARG
+
+
+def test_darray_cyclic_is_constant_size():
+    """A cyclic dimension is one strided vector, not a list of its blocks:
+    a 10^9-element cyclic(1) array over 2 processes builds instantly into a
+    one-group program, with the closed-form size, bounds and segments."""
+    g = 10 ** 9
+    t = mdt.build_type(("darray", 2, 1, [g], ["cyclic"], [None], [2], "C", ("basic", "DOUBLE")))
+    assert t.size() == (g // 2) * 8
+    assert t.extent() == (0, g * 8)
+    assert t.true_extent() == (8, (g - 1) * 8 - 8 + 8)
+    info = t.layout_info()
+    assert info["groups"] == 1 and info["device_bytes"] < 1 << 14
+    b, ln = t.iov(0, 3)
+    assert list(b) == [8, 24, 40] and list(ln) == [8, 8, 8]
+    # a partial last block: 10 elements, cyclic(3) over 2 -> rank 0 owns 0-2, 6-8; rank 1 owns 3-5, 9
+    t = mdt.build_type(("darray", 2, 1, [10], ["cyclic"], [3], [2], "C", ("basic", "INT32")))
+    b, ln = t.iov(0, 4)
+    assert list(b) == [12, 36] and list(ln) == [12, 4]
