@@ -106,6 +106,39 @@ __device__ __forceinline__ void gather_part(V4 &acc, int k, const uint8_t *s, in
     acc.w3 |= gather_word(3, k, s, n);
 }
 
+typedef uint32_t u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
+
+// OR bytes s[0..n) (0 < n <= 16 - k) into chunk positions [k, k+n) with one
+// 16-byte load from the dword holding s[0], and one more dword when the
+// bytes run past it: one or two memory instructions per piece instead of
+// one or two per word (a gather of scattered runs is bound by instructions
+// issued, each touching a different line per lane).  The bytes loaded
+// beyond s[0..n) lie in the same 4 KiB page as s[0], so no access leaves a
+// mapped page; within 20 bytes of a page end the word-by-word gather is
+// used instead.
+__device__ __forceinline__ void gather_piece(V4 &acc, int k, const uint8_t *s, int n)
+{
+    const uintptr_t u = (uintptr_t)s;
+    const uintptr_t a4 = u & ~(uintptr_t)3;
+    if ((a4 & 4095) > 4096 - 20) {
+        gather_part(acc, k, s, n);
+        return;
+    }
+    const int sh = (int)(u & 3);
+    const u32x4a4 w = *gptr((const u32x4a4 *)a4);
+    const uint32_t e = sh + n > 16 ? *gptr((const uint32_t *)(a4 + 16)) : 0u;
+    unsigned __int128 v = (((unsigned __int128)w.w << 96) | ((unsigned __int128)w.z << 64) |
+                           ((unsigned __int128)w.y << 32) | (unsigned __int128)w.x) >>
+                          (8 * sh);
+    if (sh) v |= (unsigned __int128)e << (8 * (16 - sh));
+    if (n < 16) v &= ((unsigned __int128)1 << (8 * n)) - 1;
+    v <<= 8 * k;
+    acc.w0 |= (uint32_t)v;
+    acc.w1 |= (uint32_t)(v >> 32);
+    acc.w2 |= (uint32_t)(v >> 64);
+    acc.w3 |= (uint32_t)(v >> 96);
+}
+
 // write chunk bytes [k, k+n) to d[0..n): only those bytes are stored
 __device__ __forceinline__ void scatter(const V4 &acc, int k, uint8_t *d, int n)
 {
@@ -170,8 +203,8 @@ __device__ __forceinline__ void pack_chunk(const DevLayout &L, const XferArgs &A
             take2 = l2.rem < n - take ? (int)l2.rem : n - take;
             if (take2 < 0) take2 = 0;
         }
-        if (take > 0) gather_part(acc, k, src + l.addr, take);
-        if (take2 > 0) gather_part(acc, k + take, src + l2.addr, take2);
+        if (take > 0) gather_piece(acc, k, src + l.addr, take);
+        if (take2 > 0) gather_piece(acc, k + take, src + l2.addr, take2);
         if (take > 0 && take2 > 0 && take + take2 < n) {
             p += (uint64_t)(take + take2);
             k += take + take2;
@@ -180,7 +213,7 @@ __device__ __forceinline__ void pack_chunk(const DevLayout &L, const XferArgs &A
             for (;;) {
                 int t = l.rem < n ? (int)l.rem : n;
                 if (t <= 0) break;  // unreachable for a well-formed layout; never spin
-                gather_part(acc, k, src + l.addr, t);
+                gather_piece(acc, k, src + l.addr, t);
                 p += t;
                 k += t;
                 n -= t;
@@ -925,7 +958,7 @@ __device__ __forceinline__ void runs_chunk(const XferArgs &A, const RunsCache &C
             scatter(acc, k, const_cast<uint8_t *>(typed) + addr, take);
         } else {
             if (take == 16) acc = load16(typed + addr);
-            else gather_part(acc, k, typed + addr, take);
+            else gather_piece(acc, k, typed + addr, take);
         }
         q += take;
         k += take;
