@@ -139,39 +139,41 @@ __device__ __forceinline__ void gather_piece(V4 &acc, int k, const uint8_t *s, i
     acc.w3 |= (uint32_t)(v >> 96);
 }
 
-// write chunk bytes [k, k+n) to d[0..n): only those bytes are stored
+typedef uint32_t u32x4a1 __attribute__((ext_vector_type(4), aligned(1)));
+typedef uint32_t u32x2a1 __attribute__((ext_vector_type(2), aligned(1)));
+typedef uint32_t u32a1 __attribute__((aligned(1)));
+typedef uint16_t u16a1 __attribute__((aligned(1)));
+
+// write chunk bytes [k, k+n) to d[0..n): only those bytes are stored.  The
+// piece goes out as at most one store per set bit of n (16, 8, 4, 2 and 1
+// bytes), at any alignment (global memory takes unaligned accesses; each
+// store covers piece bytes only, so neighbouring bytes are never written):
+// a scatter of scattered short runs is bound by the stores issued.
 __device__ __forceinline__ void scatter(const V4 &acc, int k, uint8_t *d, int n)
 {
-    uintptr_t u = (uintptr_t)d;
     if (n == 16) {
-        if ((u & 15) == 0) {
-            u32x4 v = {acc.w0, acc.w1, acc.w2, acc.w3};
-            *gptr((u32x4 *)d) = v;
-            return;
-        }
-        if ((u & 7) == 0) {
-            MDT_G u32x2 *p = gptr((u32x2 *)d);
-            p[0] = u32x2{acc.w0, acc.w1};
-            p[1] = u32x2{acc.w2, acc.w3};
-            return;
-        }
-        if ((u & 3) == 0) {
-            MDT_G uint32_t *p = gptr((uint32_t *)d);
-            p[0] = acc.w0; p[1] = acc.w1; p[2] = acc.w2; p[3] = acc.w3;
-            return;
-        }
-    }
-    if (n == 8 && (u & 7) == 0) {
-        *gptr((u32x2 *)d) = u32x2{dword_at(acc, k), dword_at(acc, k + 4)};
+        if (((uintptr_t)d & 15) == 0) *gptr((u32x4 *)d) = u32x4{acc.w0, acc.w1, acc.w2, acc.w3};
+        else *gptr((u32x4a1 *)d) = u32x4a1{acc.w0, acc.w1, acc.w2, acc.w3};
         return;
     }
-    int h = (int)((4 - (u & 3)) & 3);
-    if (h > n) h = n;
-    MDT_G uint8_t *g = gptr(d);
-    for (int i = 0; i < h; i++) g[i] = (uint8_t)byte_at(acc, k + i);
-    int j = h;
-    for (; j + 4 <= n; j += 4) *gptr((uint32_t *)(d + j)) = dword_at(acc, k + j);
-    for (; j < n; j++) g[j] = (uint8_t)byte_at(acc, k + j);
+    unsigned __int128 v = as128(acc) >> (8 * k);
+    int o = 0;
+    if (n & 8) {
+        *gptr((u32x2a1 *)(d + o)) = u32x2a1{(uint32_t)v, (uint32_t)(v >> 32)};
+        v >>= 64;
+        o += 8;
+    }
+    if (n & 4) {
+        *gptr((u32a1 *)(d + o)) = (uint32_t)v;
+        v >>= 32;
+        o += 4;
+    }
+    if (n & 2) {
+        *gptr((u16a1 *)(d + o)) = (uint16_t)v;
+        v >>= 16;
+        o += 2;
+    }
+    if (n & 1) *gptr(d + o) = (uint8_t)v;
 }
 
 // ---------------------------------------------------------------------------
