@@ -103,6 +103,9 @@ def parse():
     ap.add_argument("--rotate", type=int, default=4,
                     help="rotate over this many copies of the arrays so every step reads cold data")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="batched mode: skip the per-request comparison (profiling runs: the timed launches are then "
+                         "the trace's last ones)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     return ap.parse_args()
 
@@ -592,13 +595,20 @@ def main():
     batched = batches is not None
     dt, dev_s = timed_run(batched)
     value = step_bytes * args.steps / dt / 1e9
-    launches_per_step = 2 if batched else 2 * len(types)
-    dom = "batch_kernel (pack and unpack launches)" if batched else "pack and unpack launches"
+    if batched:
+        # a direction tuned to policy 3 runs each request's own kernel
+        single = [tuned[d]["policy"] == 3 for d in ("pack", "unpack")]
+        launches_per_step = sum(len(types) if x else 1 for x in single)
+        dom = ("batch_kernel" if not any(single) else "single-request kernels" if all(single)
+               else "batch_kernel and single-request kernels") + " (pack and unpack launches)"
+    else:
+        launches_per_step = 2 * len(types)
+        dom = "pack and unpack launches"
     avg_dur = dev_s / (launches_per_step * args.steps)
     bytes_per_launch = step_bytes / launches_per_step
     achieved = bytes_per_launch / avg_dur / 1e9 if avg_dur > 0 else 0.0
     other = None
-    if batched:
+    if batched and not args.no_compare:
         dt_plain, _ = timed_run(False)
         other = {"mode": "plain (one launch per request)", "value": round(step_bytes * args.steps / dt_plain / 1e9, 2),
                  "ms_per_step": round(dt_plain / args.steps * 1e3, 4)}
@@ -624,7 +634,8 @@ def main():
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic(args.workload + "/" + args.mode, dom),
                      "kernel": dom,
-                     "avg_launch_us": round(avg_dur * 1e6, 2), "bytes_per_launch": int(bytes_per_launch)},
+                     "avg_launch_us": round(avg_dur * 1e6, 2), "bytes_per_launch": int(bytes_per_launch),
+                     "launches_per_step": launches_per_step},
     }
     if other is not None:
         out["per_request"] = other

@@ -411,7 +411,10 @@ MDT_API int mdt_batch_add_copy(mdt_batch b, const void *src, mdt_count srccount,
 /* Tuning knobs of the persistent launch.  policy: 0 = static strided split
  * of tiles over workgroups, 1 = dynamic (atomic tile counter), 2 = one tile
  * per workgroup run by a kernel without the tile loop (fewer scalar
- * registers held across the tile; requires wgs_per_cu = 0).  order: 1 =
+ * registers held across the tile; requires wgs_per_cu = 0), 3 = each request
+ * runs its single-request kernel (one launch, or graph node, per request;
+ * requires wgs_per_cu = 0 and order = 0; a batch of one large request then
+ * runs exactly as a plain launch).  order: 1 =
  * tiles run in the order of the typed address they start at, so requests
  * that touch the same memory (faces sharing cache lines) run together;
  * with policies 0 and 2 the ordered tiles are dealt to the XCDs (each has
@@ -419,7 +422,7 @@ MDT_API int mdt_batch_add_copy(mdt_batch b, const void *src, mdt_count srccount,
 typedef struct mdt_batch_config {
     int tile_chunks;    /* 16-byte chunks per workgroup tile: 256, 512, 1024, 2048, 4096 */
     int wgs_per_cu;     /* persistent workgroups per compute unit, 1..16; 0: one workgroup per tile */
-    int policy;         /* 0 static, 1 dynamic, 2 one tile per workgroup (no loop) */
+    int policy;         /* 0 static, 1 dynamic, 2 one tile per workgroup (no loop), 3 per-request kernels */
     int use_graph;      /* 1 = capture and replay a HIP graph, 0 = direct launches */
     int order;          /* 0 request order, 1 typed-address order */
 } mdt_batch_config;

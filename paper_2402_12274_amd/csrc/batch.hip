@@ -46,6 +46,8 @@ struct mdt_batch_s {
     std::vector<BatchReq> reqs;
     mdt_batch_config cfg{1024, 4, 0, 1, 0};
     bool dirty = true;
+    uint64_t gen = 0;        // bumped whenever the request list changes
+    uint64_t graph_gen = ~0ull;
     int device = -1;
     int ncu = 0;
     // device buffer: header | descriptors | tile prefix
@@ -307,8 +309,40 @@ void launch_dir(mdt_batch_s *b, hipStream_t s, dim3 grid, size_t lds, unsigned l
     launch_batch_dir<POLICY, UNPACK>(grid, lds, s, H, R, tile0, b->d_order, ctr, body);
 }
 
+// Policy 3: every request with its single-request kernel (one launch per
+// request; in a graph, one node per request), pack direction first.
+void enqueue_single(mdt_batch_s *b, hipStream_t s)
+{
+    for (int dir = 0; dir < 2; dir++) {
+        for (const BatchReq &r : b->reqs) {
+            if (r.d.unpack != dir) continue;
+            DeviceTables *D = nullptr;
+            if (device_tables(r.type->comp.get(), &D) != MDT_SUCCESS) continue;  // uploaded when added
+            if (r.type2) {
+                DeviceTables *D2 = nullptr;
+                if (device_tables(r.type2->comp.get(), &D2) != MDT_SUCCESS) continue;
+                CopyArgs A{};
+                A.src = r.d.typed;
+                A.dst = r.d.packed;
+                A.off = r.d.off;
+                A.nbytes = r.d.nbytes;
+                A.nchunks = (r.d.nbytes + 15) / 16;
+                A.src_elem1 = r.d.elem1;
+                A.dst_elem1 = r.d.elem1_2;
+                (void)launch_copy(D->lay, D2->lay, A, s);
+            } else {
+                (void)launch_xfer(D->lay, make_args(r.d.typed, r.d.packed, r.d.off, r.d.nbytes), dir == 1, s);
+            }
+        }
+    }
+}
+
 void enqueue_kernels(mdt_batch_s *b, hipStream_t s)
 {
+    if (b->cfg.policy == 3) {
+        enqueue_single(b, s);
+        return;
+    }
     // one kernel per direction: a mixed batch runs its pack tiles, then its
     // unpack tiles
     for (int dir = 0; dir < 2; dir++) {
@@ -354,7 +388,7 @@ int launch(mdt_batch_s *b, hipStream_t s)
     if (!b->exec || b->graph_grid[0] != g0 || b->graph_grid[1] != g1 || b->graph_policy != b->cfg.policy ||
         b->graph_buf != b->d_buf || b->graph_lds[0] != b->lds_dir[0] || b->graph_lds[1] != b->lds_dir[1] ||
         b->graph_body[0] != b->body_dir[0] || b->graph_body[1] != b->body_dir[1] || b->graph_ordered != b->cfg.order ||
-        b->graph_order != b->d_order) {
+        b->graph_order != b->d_order || (b->cfg.policy == 3 && b->graph_gen != b->gen)) {
         release_graph(b);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
@@ -372,6 +406,7 @@ int launch(mdt_batch_s *b, hipStream_t s)
         b->graph_grid[0] = g0;
         b->graph_grid[1] = g1;
         b->graph_policy = b->cfg.policy;
+        b->graph_gen = b->gen;
         for (int d = 0; d < 2; d++) {
             b->graph_lds[d] = b->lds_dir[d];
             b->graph_body[d] = b->body_dir[d];
@@ -394,8 +429,8 @@ bool valid_cfg(const mdt_batch_config &c)
 {
     bool tc = c.tile_chunks == 256 || c.tile_chunks == 512 || c.tile_chunks == 1024 || c.tile_chunks == 2048 ||
               c.tile_chunks == 4096;
-    return tc && c.wgs_per_cu >= 0 && c.wgs_per_cu <= 16 && c.policy >= 0 && c.policy <= 2 &&
-           (c.policy != 2 || c.wgs_per_cu == 0) &&
+    return tc && c.wgs_per_cu >= 0 && c.wgs_per_cu <= 16 && c.policy >= 0 && c.policy <= 3 &&
+           (c.policy < 2 || c.wgs_per_cu == 0) && (c.policy != 3 || c.order == 0) &&
            (c.use_graph == 0 || c.use_graph == 1) && (c.order == 0 || c.order == 1);
 }
 
@@ -427,6 +462,7 @@ int add_req(mdt_batch b, TypeNode *t, const ReqDesc &d, int32_t lds, TypeNode *t
         return MDT_ERR_NO_MEM;
     }
     b->dirty = true;
+    b->gen++;
     return MDT_SUCCESS;
 }
 
@@ -457,6 +493,7 @@ MDT_API int mdt_batch_clear(mdt_batch b)
     }
     b->reqs.clear();
     b->dirty = true;
+    b->gen++;
     return MDT_SUCCESS;
 }
 
@@ -616,11 +653,13 @@ MDT_API int mdt_batch_autotune(mdt_batch b, mdt_stream s, mdt_batch_config *best
     int rc = MDT_SUCCESS;
     for (int graph = 0; graph < 2 && !rc; graph++)
         for (int ord = 0; ord < 2 && !rc; ord++)
-            for (int policy = 0; policy < 3 && !rc; policy++)
+            for (int policy = 0; policy < 4 && !rc; policy++)
                 for (int tc : tiles)
                     for (int w : occ) {
                         if (policy == 1 && w == 0) continue;  // nothing to balance with a workgroup per tile
                         if (policy == 2 && w != 0) continue;  // the loop-free kernel takes one tile per workgroup
+                        // single-request kernels: their own tiles, no order
+                        if (policy == 3 && (w != 0 || tc != 1024 || ord != 0)) continue;
                         mdt_batch_config c{tc, w, policy, graph, ord};
                         mdt_batch_set_config(b, &c);
                         rc = launch(b, s->s);  // warm-up (uploads, graph capture)

@@ -63,13 +63,14 @@ def test_batch_config_validation():
     from paper_2402_12274_amd import mdt
 
     b = mdt.Batch()
-    good = [(256, 0, 0, 0, 0), (4096, 16, 1, 1, 1), (1024, 4, 0, 0, 1), (1024, 0, 2, 1, 1), (512, 1, 1, 1, 0)]
+    good = [(256, 0, 0, 0, 0), (4096, 16, 1, 1, 1), (1024, 4, 0, 0, 1), (1024, 0, 2, 1, 1), (1024, 0, 3, 1, 0),
+            (512, 1, 1, 1, 0)]
     for cfg in good:
         b.set_config(mdt.BatchConfig(*cfg))
         got = b.get_config()
         assert tuple(getattr(got, f) for f, _ in got._fields_) == cfg
     bad = [(128, 0, 0, 0, 0), (1000, 0, 0, 0, 0), (1024, -1, 0, 0, 0), (1024, 17, 0, 0, 0), (1024, 4, 2, 0, 0),
-           (1024, 4, 0, 2, 0), (1024, 4, 0, 0, 2), (1024, 4, 0, 0, -1), (1024, 4, 2, 0, 0), (1024, 0, 3, 0, 0)]
+           (1024, 4, 0, 2, 0), (1024, 4, 0, 0, 2), (1024, 4, 0, 0, -1), (1024, 4, 2, 0, 0), (1024, 0, 4, 0, 0), (1024, 4, 3, 0, 0), (1024, 0, 3, 0, 1)]
     for cfg in bad:
         try:
             b.set_config(mdt.BatchConfig(*cfg))

@@ -113,7 +113,8 @@ def test_batch_equals_alone(env):
     b = mdt.Batch()
     for (t, src, n), o in zip(plan, offs):
         assert b.add_pack(src.data_ptr(), 1, t, 0, out.data_ptr() + int(o) + 3, n) == n
-    for policy, wgs, order in ((0, 4, 0), (1, 4, 0), (0, 0, 0), (0, 4, 1), (1, 2, 1), (0, 0, 1), (2, 0, 0), (2, 0, 1)):
+    for policy, wgs, order in ((0, 4, 0), (1, 4, 0), (0, 0, 0), (0, 4, 1), (1, 2, 1), (0, 0, 1), (2, 0, 0), (2, 0, 1),
+                               (3, 0, 0)):
         for graph in (1, 0):
             for tc in (256, 4096):
                 note(f"batch policy={policy} wgs={wgs} order={order} graph={graph} tile={tc}")
@@ -177,7 +178,7 @@ def test_batch_mixed_directions(env):
         dexp.append(e)
         dsts.append(to_dev(canary))
     ms = mdt.Stream(torch.cuda.current_stream().cuda_stream)
-    for wgs, order, pol in ((0, 0, 0), (2, 0, 0), (0, 1, 0), (4, 1, 0), (0, 0, 2), (0, 1, 2)):
+    for wgs, order, pol in ((0, 0, 0), (2, 0, 0), (0, 1, 0), (4, 1, 0), (0, 0, 2), (0, 1, 2), (0, 0, 3)):
         note(f"mixed-direction batch wgs={wgs} order={order} policy={pol}")
         for d, o in zip(dsts, orc):
             d.fill_(0x33)
@@ -213,7 +214,7 @@ def test_batch_single_body_kernels(env):
         types = [mdt.build_type(sp) for sp in specs]
         kind, rec = expect_body[name]
         assert all(t.layout_info()["kind"] == kind and t.layout_info()["records"] == rec for t in types), name
-        for wgs, order, pol in ((0, 0, 0), (4, 1, 0), (0, 0, 2)):
+        for wgs, order, pol in ((0, 0, 0), (4, 1, 0), (0, 0, 2), (0, 0, 3)):
             note(f"single-body batch {name} wgs={wgs} order={order} policy={pol}")
             bp, bu = mdt.Batch(), mdt.Batch()
             keep = []
@@ -330,3 +331,37 @@ def test_server_budget_defers_and_failures_are_isolated(env):
     more = [srv.submit_pack(src.data_ptr(), 1, t, 0, -1) for _ in range(5)]
     srv.close()
     assert all(h for h in more)
+
+
+def test_single_request_policy_graph_follows_requests(env):
+    """Policy 3 captures each request's own kernel launch (its arguments
+    are in the graph), so a graph replay after the batch's requests change
+    must be a new capture: the new destination is written, the old one is
+    left alone."""
+    torch, mdt = env
+    from gpu_util import first_diff, note, to_dev, to_host, zeros_dev
+
+    note("policy 3 graph after the requests change")
+    spec = inputs.particle_struct()
+    t = mdt.build_type(spec)
+    o = obuild(spec)
+    count = 3001
+    h = inputs.random_bytes(count * 40, seed=91)
+    full = o.pack(h, 0, count)
+    src = to_dev(h)
+    out1, out2 = zeros_dev(full.size, 0), zeros_dev(full.size, 0)
+    ms = mdt.Stream(torch.cuda.current_stream().cuda_stream)
+    b = mdt.Batch()
+    b.set_config(mdt.BatchConfig(1024, 0, 3, 1, 0))
+    b.add_pack(src.data_ptr(), count, t, 0, out1.data_ptr(), -1)
+    b.launch(ms)
+    torch.cuda.synchronize()
+    assert first_diff(to_host(out1), full) is None
+    out1.fill_(0)
+    b.clear()
+    b.add_pack(src.data_ptr(), count, t, 0, out2.data_ptr(), -1)
+    for _ in range(2):
+        b.launch(ms)
+        torch.cuda.synchronize()
+    assert first_diff(to_host(out2), full) is None
+    assert not to_host(out1).any()

@@ -208,7 +208,7 @@ def test_copy_requests_in_a_batch():
     rh = inputs.random_bytes(5000 * 40, seed=52)
     rexp_pack = obuild(rec).pack(rh, 0, 5000)
     ms = mdt.Stream(torch.cuda.current_stream().cuda_stream)
-    for wgs, order, pol in ((0, 0, 0), (4, 1, 0), (0, 0, 2)):
+    for wgs, order, pol in ((0, 0, 0), (4, 1, 0), (0, 0, 2), (0, 0, 3)):
         note(f"batch with copies wgs={wgs} order={order} policy={pol}")
         arr = to_dev(host)
         rsrc = to_dev(rh)
