@@ -8,7 +8,8 @@
 // requests first) and the per-request first-tile prefix out in device
 // memory, and runs one grid per direction: persistent (workgroups per CU x
 // CUs) pulling tiles in a static strided order or from an atomic counter, or
-// one workgroup per tile.  Tiles run in request order or in the order of the
+// one workgroup per tile (with or without the tile loop); or it runs each
+// request's own single-request kernel.  Tiles run in request order or in the order of the
 // typed address they start at (requests that share cache lines then run
 // together, neighbours on the same XCD).  Each tile finds its request by
 // binary search over the prefix, reads the request's layout program through
