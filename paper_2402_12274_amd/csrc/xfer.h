@@ -35,6 +35,18 @@ __device__ __forceinline__ const MDT_G T *gptr(const T *p)
     return (const MDT_G T *)p;
 }
 
+typedef uint32_t u32x4a1l __attribute__((ext_vector_type(4), aligned(1)));
+
+// 16 bytes at any alignment with one load (global memory takes unaligned
+// loads; every byte loaded is one of the 16).  Used where gathers of short
+// scattered runs are bound by instructions issued; the chunk kernels keep
+// load16, whose alignment cases cost fewer scalar registers there.
+__device__ __forceinline__ V4 load16_any(const uint8_t *s)
+{
+    const u32x4a1l v = *gptr((const u32x4a1l *)s);
+    return V4{v.x, v.y, v.z, v.w};
+}
+
 // Byte / dword extraction at a variable byte position of the chunk, as
 // 128-bit shifts (funnel shifts in registers; an indexed select would be
 // turned into a per-lane memory array).
@@ -959,7 +971,7 @@ __device__ __forceinline__ void runs_chunk(const XferArgs &A, const RunsCache &C
         if (UNPACK) {
             scatter(acc, k, const_cast<uint8_t *>(typed) + addr, take);
         } else {
-            if (take == 16) acc = load16(typed + addr);
+            if (take == 16) acc = load16_any(typed + addr);
             else gather_piece(acc, k, typed + addr, take);
         }
         q += take;
