@@ -72,8 +72,10 @@ static int sync_event(mdt_request r)
 static int drive_general(int n, const mdt_request *reqs)
 {
     std::vector<void *> states;
+    std::vector<GRequest *> open;
+    std::vector<mdt_grequest_wait_fn> seen;
     for (;;) {
-        std::vector<GRequest *> open;
+        open.clear();
         bool others = false;  // incomplete requests without a wait_fn
         for (int i = 0; i < n; i++) {
             GRequest *g = general_of(reqs[i]);
@@ -86,7 +88,7 @@ static int drive_general(int n, const mdt_request *reqs)
         bool progress = false;
         // wait_fn groups, in order of first appearance; with requests that
         // need polling alongside, each group waits a bounded time
-        std::vector<mdt_grequest_wait_fn> seen;
+        seen.clear();
         for (GRequest *g : open) {
             if (!g->wait_fn) continue;
             bool dup = false;

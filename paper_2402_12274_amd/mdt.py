@@ -472,7 +472,9 @@ def waitall(reqs):
 _GREQS = {}
 _GREQ_NEXT = [1]
 # one C wrapper per Python wait callable: requests that share the callable
-# share the C function pointer, so the library groups them into one call
+# share the C function pointer, so the library groups them into one call.
+# Wrappers live as long as the process (pass the same function object, not a
+# fresh lambda or bound method per request, to share one and to group).
 _WAIT_WRAPPERS = {}
 
 
