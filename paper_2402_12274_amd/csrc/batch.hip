@@ -275,6 +275,12 @@ int stage(mdt_batch_s *b, hipStream_t s)
         if (rc) return rc;
     }
     H.ordered = b->cfg.order ? 1 : 0;
+    {
+        int64_t packed = 0;
+        for (auto &r : b->reqs)
+            if (!r.d.unpack && !r.type2) packed += r.d.nbytes;
+        H.keep_packed = packed <= KEEP_PACKED_MAX ? 1 : 0;
+    }
     H.nslots_dir[0] = b->nslots_dir[0];
     H.nslots_dir[1] = b->nslots_dir[1];
     std::memcpy(b->h_stage, &H, sizeof H);

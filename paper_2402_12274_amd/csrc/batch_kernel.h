@@ -39,6 +39,7 @@ struct BatchHeader {
     int64_t tile_chunks;
     int64_t ordered;        // 1: slots map to tiles through the order table
     int64_t nslots_dir[2];  // order-table slots per direction (>= tiles; -1 entries are empty)
+    int64_t keep_packed;    // the pack direction's output fits KEEP_PACKED_MAX: cached stores
 };
 
 // Chunks [c0, cend) of one request, with the single-request bodies.
@@ -179,6 +180,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restric
             A.nchunks = D.nchunks;
             A.tile_chunks = T;
             A.elem1 = D.elem1;
+            A.keep = (int32_t)H->keep_packed;
             int64_t c0 = (tile - tile0[lo]) * T;
             int64_t cend = c0 + T < D.nchunks ? c0 + T : D.nchunks;
             run_tile<UNPACK, BODY>(L, A, D.body, D.kind, c0, cend, lds_dyn, D);

@@ -301,6 +301,7 @@ int launch_xfer(const DevLayout &L, const XferArgs &A0, bool unpack, hipStream_t
     if (A0.nbytes == 0 || L.kind == KIND_EMPTY) return MDT_SUCCESS;
     XferArgs A = A0;
     A.elem1 = A.off + A.nbytes <= L.size;
+    A.keep = !unpack && A.nbytes <= KEEP_PACKED_MAX;
     if (use_dense(L, A, unpack)) {
         A.tile_chunks = L.rec.tile_chunks;
         int64_t grid = launch_grid((A.nchunks + A.tile_chunks - 1) / A.tile_chunks);

@@ -47,6 +47,13 @@ __device__ __forceinline__ V4 load16_any(const uint8_t *s)
     return V4{v.x, v.y, v.z, v.w};
 }
 
+// A 16-byte chunk of the packed output: cached or streaming (A.keep).
+__device__ __forceinline__ void store_out(const XferArgs &A, uint8_t *dst, const u32x4 &v)
+{
+    if (A.keep) *gptr((u32x4 *)dst) = v;
+    else __builtin_nontemporal_store(v, gptr((u32x4 *)dst));
+}
+
 // Byte / dword extraction at a variable byte position of the chunk, as
 // 128-bit shifts (funnel shifts in registers; an indexed select would be
 // turned into a per-lane memory array).
@@ -239,7 +246,7 @@ __device__ __forceinline__ void pack_chunk(const DevLayout &L, const XferArgs &A
     uint8_t *dst = A.packed - A.head + 16 * c;
     if (a == lo && b == lo + 16) {
         u32x4 v = {acc.w0, acc.w1, acc.w2, acc.w3};
-        __builtin_nontemporal_store(v, gptr((u32x4 *)dst));
+        store_out(A, dst, v);
     } else {
         for (int i = (int)(a - lo); i < (int)(b - lo); i++) gptr(dst)[i] = (uint8_t)byte_at(acc, i);
     }
@@ -314,7 +321,7 @@ __device__ __forceinline__ bool pack_first(const DevLayout &L, const XferArgs &A
 __device__ __forceinline__ void store_chunk(const XferArgs &A, int64_t c, const V4 &acc)
 {
     u32x4 v = {acc.w0, acc.w1, acc.w2, acc.w3};
-    __builtin_nontemporal_store(v, gptr((u32x4 *)(A.packed - A.head + 16 * c)));
+    store_out(A, (A.packed - A.head + 16 * c), v);
 }
 
 // Whole tile inside one run: the typed address of packed byte lo (relative
@@ -663,7 +670,7 @@ __device__ __forceinline__ void dense_pack_tile_b(const DevLayout &L, const Xfer
             uint32_t w2 = dense_word(tab, span, base, X, U, q, er);
             uint32_t w3 = dense_word(tab, span, base, X, U, q, er);
             u32x4 v = {w0, w1, w2, w3};
-            __builtin_nontemporal_store(v, gptr((u32x4 *)(A.packed - A.head + 16 * c)));
+            store_out(A, (A.packed - A.head + 16 * c), v);
         } else {
             uint8_t *dst = A.packed - A.head + 16 * c;
             for (int i = (int)(a - lo); i < (int)(b - lo); i++) {
@@ -776,7 +783,7 @@ __device__ __forceinline__ void dense_pack_tile_c(const DevLayout &L, const Xfer
             const uint4 o0 = e[0], o1 = e[1], o2 = e[2], o3 = e[3];
             u32x4 v = {lds_gather4(span, rb, o0), lds_gather4(span, rb, o1), lds_gather4(span, rb, o2),
                        lds_gather4(span, rb, o3)};
-            __builtin_nontemporal_store(v, gptr((u32x4 *)(out + 16 * k)));
+            store_out(A, (out + 16 * k), v);
         } else {
             const int32_t a = pr > 0 ? pr : 0, b = pr + 16 < npk ? pr + 16 : npk;
             for (int32_t i = a; i < b; i++) {
@@ -983,7 +990,7 @@ __device__ __forceinline__ void runs_chunk(const XferArgs &A, const RunsCache &C
         uint8_t *dst = A.packed - A.head + 16 * c;
         if (a == lo && b == lo + 16) {
             u32x4 v = {acc.w0, acc.w1, acc.w2, acc.w3};
-            __builtin_nontemporal_store(v, gptr((u32x4 *)dst));
+            store_out(A, dst, v);
         } else {
             for (int j = (int)(a - lo); j < (int)(b - lo); j++) gptr(dst)[j] = (uint8_t)byte_at(acc, j);
         }
