@@ -388,11 +388,22 @@ MDT_API int mdt_cancel(mdt_request req);
 
 /* ---------------------------------------------------------------------
  * Batches: many pack/unpack requests of mixed types and sizes executed by
- * one persistent kernel launch, captured once in a HIP graph and replayed.
- * Requests are described on the host; mdt_batch_launch uploads the
- * descriptors (in stream order) and runs them.  Every request's bytes are
+ * one kernel launch per direction (pack requests and copies first, then
+ * unpack requests).  How that launch runs is the batch's configuration
+ * (mdt_batch_config below): a persistent grid or one workgroup per tile,
+ * each either launched directly or captured once in a HIP graph and
+ * replayed; mdt_batch_autotune picks among them by timing the batch, and
+ * mdt_batch_get_config reports the choice.  Requests are described on the
+ * host; mdt_batch_launch uploads the descriptors (in stream order, only
+ * when the batch changed) and runs them.  Every request's bytes are
  * identical to the same request run alone.  Destinations of different
- * requests must not overlap. */
+ * requests must not overlap, except where the overlapping bytes receive
+ * equal values (the faces of one array unpacked from one exchange meet
+ * along their edges): the writes are byte-exact, so their order does not
+ * matter then.  A batch may be launched on any stream: a
+ * launch on a different stream than the batch's previous launch waits on
+ * the device for that launch first (the batch's device-side descriptors
+ * are shared by its launches). */
 MDT_API int mdt_batch_create(mdt_batch *b);
 MDT_API int mdt_batch_free(mdt_batch *b);
 /* Remove all requests (the batch and its captured graph are reused). */

@@ -56,6 +56,9 @@ struct mdt_batch_s {
     size_t cap = 0;  // requests the buffer holds
     uint8_t *h_stage = nullptr;  // pinned staging of the same layout
     hipEvent_t staged = nullptr; // the last upload from h_stage has been consumed
+    hipEvent_t done = nullptr;   // recorded after every (tracked) launch
+    hipStream_t last_stream = nullptr;  // stream of the last tracked launch
+    bool last_set = false;
     unsigned long long *d_counter = nullptr;  // [2] tile counters, one per direction
     int64_t ntiles_dir[2] = {0, 0};
     int64_t nslots_dir[2] = {0, 0};  // order-table slots per direction (ordered schedule)
@@ -137,6 +140,7 @@ int init_device(mdt_batch_s *b)
         b->ncu = 256;
     if (hipMalloc((void **)&b->d_counter, 2 * sizeof(unsigned long long)) != hipSuccess) return MDT_ERR_NO_MEM;
     if (hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) return MDT_ERR_HIP;
+    if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) return MDT_ERR_HIP;
     if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) return MDT_ERR_HIP;
     return MDT_SUCCESS;
 }
@@ -317,17 +321,21 @@ void launch_dir(mdt_batch_s *b, hipStream_t s, dim3 grid, size_t lds, unsigned l
 }
 
 // Policy 3: every request with its single-request kernel (one launch per
-// request; in a graph, one node per request), pack direction first.
-void enqueue_single(mdt_batch_s *b, hipStream_t s)
+// request; in a graph, one node per request), pack direction first.  The
+// first failure stops the enqueue and is returned (requests already enqueued
+// still run).
+int enqueue_single(mdt_batch_s *b, hipStream_t s)
 {
     for (int dir = 0; dir < 2; dir++) {
         for (const BatchReq &r : b->reqs) {
             if (r.d.unpack != dir) continue;
             DeviceTables *D = nullptr;
-            if (device_tables(r.type->comp.get(), &D) != MDT_SUCCESS) continue;  // uploaded when added
+            int rc = device_tables(r.type->comp.get(), &D);
+            if (rc) return rc;
             if (r.type2) {
                 DeviceTables *D2 = nullptr;
-                if (device_tables(r.type2->comp.get(), &D2) != MDT_SUCCESS) continue;
+                rc = device_tables(r.type2->comp.get(), &D2);
+                if (rc) return rc;
                 CopyArgs A{};
                 A.src = r.d.typed;
                 A.dst = r.d.packed;
@@ -336,20 +344,19 @@ void enqueue_single(mdt_batch_s *b, hipStream_t s)
                 A.nchunks = (r.d.nbytes + 15) / 16;
                 A.src_elem1 = r.d.elem1;
                 A.dst_elem1 = r.d.elem1_2;
-                (void)launch_copy(D->lay, D2->lay, A, s);
+                rc = launch_copy(D->lay, D2->lay, A, s);
             } else {
-                (void)launch_xfer(D->lay, make_args(r.d.typed, r.d.packed, r.d.off, r.d.nbytes), dir == 1, s);
+                rc = launch_xfer(D->lay, make_args(r.d.typed, r.d.packed, r.d.off, r.d.nbytes), dir == 1, s);
             }
+            if (rc) return rc;
         }
     }
+    return MDT_SUCCESS;
 }
 
-void enqueue_kernels(mdt_batch_s *b, hipStream_t s)
+int enqueue_kernels(mdt_batch_s *b, hipStream_t s)
 {
-    if (b->cfg.policy == 3) {
-        enqueue_single(b, s);
-        return;
-    }
+    if (b->cfg.policy == 3) return enqueue_single(b, s);
     // one kernel per direction: a mixed batch runs its pack tiles, then its
     // unpack tiles
     for (int dir = 0; dir < 2; dir++) {
@@ -372,62 +379,90 @@ void enqueue_kernels(mdt_batch_s *b, hipStream_t s)
             if (dir) launch_dir<0, 1>(b, s, grid, lds, ctr, body);
             else launch_dir<0, 0>(b, s, grid, lds, ctr, body);
         }
-    }
-}
-
-int launch(mdt_batch_s *b, hipStream_t s)
-{
-    int rc = init_device(b);
-    if (rc) return rc;
-    rc = stage(b, s);
-    if (rc) return rc;
-    if (b->ntiles_dir[0] + b->ntiles_dir[1] == 0) return MDT_SUCCESS;
-    const int g0 = (b->dirs & 1) ? grid_of(b, 0) : 0, g1 = (b->dirs & 2) ? grid_of(b, 1) : 0;
-    if (!b->cfg.use_graph) {
-        enqueue_kernels(b, s);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) {
             set_hip_error((int)e);
             return MDT_ERR_HIP;
         }
-        return MDT_SUCCESS;
-    }
-    if (!b->exec || b->graph_grid[0] != g0 || b->graph_grid[1] != g1 || b->graph_policy != b->cfg.policy ||
-        b->graph_buf != b->d_buf || b->graph_lds[0] != b->lds_dir[0] || b->graph_lds[1] != b->lds_dir[1] ||
-        b->graph_body[0] != b->body_dir[0] || b->graph_body[1] != b->body_dir[1] || b->graph_ordered != b->cfg.order ||
-        b->graph_order != b->d_order || (b->cfg.policy == 3 && b->graph_gen != b->gen)) {
-        release_graph(b);
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            enqueue_kernels(b, b->cap_stream);
-            e = hipStreamEndCapture(b->cap_stream, &g);
-        }
-        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
-        if (g) (void)hipGraphDestroy(g);
-        if (e != hipSuccess) {
-            set_hip_error((int)e);
-            b->exec = nullptr;
-            return MDT_ERR_HIP;
-        }
-        b->graph_grid[0] = g0;
-        b->graph_grid[1] = g1;
-        b->graph_policy = b->cfg.policy;
-        b->graph_gen = b->gen;
-        for (int d = 0; d < 2; d++) {
-            b->graph_lds[d] = b->lds_dir[d];
-            b->graph_body[d] = b->body_dir[d];
-        }
-        b->graph_buf = b->d_buf;
-        b->graph_ordered = b->cfg.order;
-        b->graph_order = b->d_order;
-    }
-    hipError_t e = hipGraphLaunch(b->exec, s);
-    if (e != hipSuccess) {
-        set_hip_error((int)e);
-        return MDT_ERR_HIP;
     }
     return MDT_SUCCESS;
+}
+
+// A batch owns one descriptor buffer, one order table and one pair of tile
+// counters; a launch on another stream than the previous one first waits
+// (on the device) for the previous launch, so a new upload or counter reset
+// never lands under a kernel that still reads them.  The server's batches
+// stay on one stream and skip the bookkeeping (track = false).
+int launch(mdt_batch_s *b, hipStream_t s, bool track = true)
+{
+    int rc = init_device(b);
+    if (rc) return rc;
+    if (track && b->last_set && s != b->last_stream) {
+        hipError_t e = hipStreamWaitEvent(s, b->done, 0);
+        if (e != hipSuccess) {
+            set_hip_error((int)e);
+            return MDT_ERR_HIP;
+        }
+    }
+    rc = stage(b, s);
+    if (rc) return rc;
+    if (b->ntiles_dir[0] + b->ntiles_dir[1] == 0) return MDT_SUCCESS;
+    const int g0 = (b->dirs & 1) ? grid_of(b, 0) : 0, g1 = (b->dirs & 2) ? grid_of(b, 1) : 0;
+    if (!b->cfg.use_graph) {
+        rc = enqueue_kernels(b, s);
+    } else {
+        if (!b->exec || b->graph_grid[0] != g0 || b->graph_grid[1] != g1 || b->graph_policy != b->cfg.policy ||
+            b->graph_buf != b->d_buf || b->graph_lds[0] != b->lds_dir[0] || b->graph_lds[1] != b->lds_dir[1] ||
+            b->graph_body[0] != b->body_dir[0] || b->graph_body[1] != b->body_dir[1] ||
+            b->graph_ordered != b->cfg.order || b->graph_order != b->d_order ||
+            (b->cfg.policy == 3 && b->graph_gen != b->gen)) {
+            release_graph(b);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                rc = enqueue_kernels(b, b->cap_stream);
+                e = hipStreamEndCapture(b->cap_stream, &g);  // ends the capture whatever rc is
+            }
+            if (e == hipSuccess && rc == MDT_SUCCESS) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            if (rc == MDT_SUCCESS && e != hipSuccess) {
+                set_hip_error((int)e);
+                rc = MDT_ERR_HIP;
+            }
+            if (rc) {
+                b->exec = nullptr;
+                return rc;
+            }
+            b->graph_grid[0] = g0;
+            b->graph_grid[1] = g1;
+            b->graph_policy = b->cfg.policy;
+            b->graph_gen = b->gen;
+            for (int d = 0; d < 2; d++) {
+                b->graph_lds[d] = b->lds_dir[d];
+                b->graph_body[d] = b->body_dir[d];
+            }
+            b->graph_buf = b->d_buf;
+            b->graph_ordered = b->cfg.order;
+            b->graph_order = b->d_order;
+        }
+        hipError_t e = hipGraphLaunch(b->exec, s);
+        if (e != hipSuccess) {
+            set_hip_error((int)e);
+            rc = MDT_ERR_HIP;
+        }
+    }
+    if (track) {
+        // recorded even after a failed enqueue: what was enqueued still runs
+        hipError_t e = hipEventRecord(b->done, s);
+        if (e == hipSuccess) {
+            b->last_stream = s;
+            b->last_set = true;
+        } else if (rc == MDT_SUCCESS) {
+            set_hip_error((int)e);
+            rc = MDT_ERR_HIP;
+        }
+    }
+    return rc;
 }
 
 bool valid_batch(mdt_batch b) { return b && b->magic == BATCH_MAGIC; }
@@ -477,7 +512,7 @@ int add_req(mdt_batch b, TypeNode *t, const ReqDesc &d, int32_t lds, TypeNode *t
 
 namespace mdt {
 // used by the serving loop
-int batch_launch_internal(mdt_batch b, hipStream_t s) { return launch(b, s); }
+int batch_launch_internal(mdt_batch b, hipStream_t s) { return launch(b, s, false); }
 }  // namespace mdt
 
 extern "C" {
@@ -517,6 +552,7 @@ MDT_API int mdt_batch_free(mdt_batch *pb)
     if (b->d_order) (void)hipFree(b->d_order);
     if (b->h_order) (void)hipHostFree(b->h_order);
     if (b->staged) (void)hipEventDestroy(b->staged);
+    if (b->done) (void)hipEventDestroy(b->done);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     b->magic = 0;
     delete b;

@@ -11,6 +11,16 @@
 //                its own streams, admission by memory);
 //   per-request: every request is one plain stream-ordered launch on stream
 //                (id mod nstreams), completion polled through its event.
+//
+// Destinations never overlap while requests are in flight (the library's
+// contract): every request that writes caller memory -- an unpack's typed
+// span, a per-request pack's output -- takes its own range of a device ring,
+// handed out in issue order and returned when the request completes.  When
+// the ring is full the issuer reaps until the oldest range is free (counted
+// as ring waits; the wait is part of the waiting requests' latency, since
+// latency runs from the scheduled arrival).  Sampled requests write to fixed
+// caller buffers instead, so their bytes can be compared after the run
+// (served pack results are copied out of the server's arena before release).
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -32,9 +42,12 @@ struct mdt_lg_req {
     int32_t type_index;
     int64_t count;
     int64_t target;       // bytes [0, target) of the stream
-    const void *typed;    // pack source / unpack destination origin
+    const void *typed;    // pack source origin
     const void *packed;   // unpack input
-    void *out;            // pack output (per-request mode)
+    void *fixed;          // sampled request: its own destination (pack output, or the unpack
+                          // span's first byte); NULL: a range of the ring
+    int64_t span;         // bytes the request writes: pack output (target), or the unpack's typed span
+    int64_t origin_off;   // unpack: the origin is the span's first byte + origin_off (= -true_lb)
 };
 
 struct mdt_lg_result {
@@ -46,6 +59,8 @@ struct mdt_lg_result {
     int64_t late_issues;  // requests issued more than 50 us after their scheduled time
     double p50_queue_us, p99_queue_us, p50_run_us, p99_run_us;  // served: server-side split
     double p50_issue_us, p99_issue_us;  // duration of the submit / enqueue call
+    int64_t ring_waits;   // issues that waited for a ring range to come free
+    double ring_wait_us;  // total time spent waiting for the ring
 };
 
 }  // extern "C"
@@ -88,32 +103,92 @@ void summarize(std::vector<double> &lat, mdt_lg_result *r)
     r->mean_us = s / (double)lat.size();
 }
 
+
+// Destination ring: ranges handed out in issue order over [0, cap), freed
+// in any order; the live ranges always form one circular run from the
+// oldest (tail) to head.
+struct Ring {
+    uint8_t *base = nullptr;
+    int64_t cap = 0, head = 0;
+    struct Range {
+        int64_t off, len;
+        bool done;
+    };
+    std::deque<Range> live;
+    uint64_t first_id = 0;  // id of live.front()
+    static int64_t round(int64_t n) { return std::max<int64_t>(256, (n + 255) / 256 * 256); }
+    // returns the range id, or -1 when it does not fit now
+    int64_t alloc(int64_t n, int64_t *off)
+    {
+        n = round(n);
+        if (n > cap) return -2;  // never fits
+        int64_t at;
+        if (live.empty()) {
+            at = 0;
+        } else {
+            const int64_t tail = live.front().off;
+            if (head > tail) {  // occupied [tail, head)
+                if (head + n <= cap) at = head;
+                else if (n <= tail) at = 0;
+                else return -1;
+            } else {            // wrapped: occupied [tail, cap) and [0, head)
+                if (head + n <= tail) at = head;
+                else return -1;
+            }
+        }
+        head = at + n;
+        live.push_back({at, n, false});
+        *off = at;
+        return (int64_t)(first_id + live.size() - 1);
+    }
+    void free(int64_t id)
+    {
+        if (id < 0) return;
+        live[(size_t)((uint64_t)id - first_id)].done = true;
+        while (!live.empty() && live.front().done) {
+            live.pop_front();
+            first_id++;
+        }
+        if (live.empty()) head = 0;
+    }
+};
+
 }  // namespace
 
 extern "C" {
 
 // Serve the trace through an mdt_server (progress thread on).  Pack outputs
-// live in the server's arena and are released as soon as they complete.
+// live in the server's arena and are released as soon as they complete
+// (sampled ones are first copied to their fixed buffer); unpack spans come
+// from the ring [ring, ring + ring_bytes).
 // lat_out (optional, n entries): each request's latency in us, -1 if it failed.
 __attribute__((visibility("default"))) int mdt_lg_run_served(const mdt_lg_req *reqs, int64_t n, const mdt_type *types,
-                                                             const mdt_server_config *cfg, mdt_lg_result *res,
-                                                             double *lat_out)
+                                                             const mdt_server_config *cfg, void *ring_base,
+                                                             int64_t ring_bytes, mdt_lg_result *res, double *lat_out)
 {
     std::memset(res, 0, sizeof *res);
     if (lat_out)
         for (int64_t k = 0; k < n; k++) lat_out[k] = -1.0;
+    Ring ring;
+    ring.base = static_cast<uint8_t *>(ring_base);
+    ring.cap = ring_bytes;
+    hipStream_t cs = nullptr;  // copies of sampled pack results
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return MDT_ERR_HIP;
     mdt_server srv = nullptr;
     int rc = mdt_server_create(cfg, &srv);
-    if (rc) return rc;
-    rc = mdt_server_start_progress_thread(srv);
+    if (rc == MDT_SUCCESS) {
+        rc = mdt_server_start_progress_thread(srv);
+        if (rc) mdt_server_free(&srv);
+    }
     if (rc) {
-        mdt_server_free(&srv);
+        (void)hipStreamDestroy(cs);
         return rc;
     }
     struct Pending {
         mdt_request r;
         double t_arrive;
         int64_t idx;
+        int64_t range;  // ring range id, or -1
     };
     std::deque<Pending> pend;
     std::vector<double> lat, issue;
@@ -122,6 +197,7 @@ __attribute__((visibility("default"))) int mdt_lg_run_served(const mdt_lg_req *r
     const double t0 = now_us() + 1000.0;
     double last_done = t0;
     int64_t i = 0;
+    int err = MDT_SUCCESS;
     auto reap = [&](bool all) {
         while (!pend.empty()) {
             // complete in any order: scan a window of the oldest requests
@@ -135,19 +211,28 @@ __attribute__((visibility("default"))) int mdt_lg_run_served(const mdt_lg_req *r
                 int st = 0;
                 double l = 0;
                 int64_t nb = 0;
-                mdt_server_request_result(srv, pend[k].r, &st, nullptr, &nb, &l);
+                void *pk = nullptr;
+                mdt_server_request_result(srv, pend[k].r, &st, &pk, &nb, &l);
                 double t = now_us();
+                const mdt_lg_req &q = reqs[pend[k].idx];
                 if (st == MDT_SUCCESS) {
                     res->completed++;
                     res->bytes += nb;
                     lat.push_back(t - pend[k].t_arrive);
                     if (lat_out) lat_out[pend[k].idx] = t - pend[k].t_arrive;
+                    if (!q.unpack && q.fixed && nb > 0) {
+                        // a sampled result leaves the arena before it is released
+                        hipError_t e = hipMemcpyAsync(q.fixed, pk, (size_t)nb, hipMemcpyDeviceToDevice, cs);
+                        if (e == hipSuccess) e = hipStreamSynchronize(cs);
+                        if (e != hipSuccess) err = MDT_ERR_HIP;
+                    }
                 } else {
                     res->failed++;
                 }
                 last_done = std::max(last_done, t);
                 mdt_server_request_release(srv, &pend[k].r);
                 pend[k].r = nullptr;
+                ring.free(pend[k].range);
                 progressed = true;
             }
             while (!pend.empty() && pend.front().r == nullptr) pend.pop_front();
@@ -158,18 +243,40 @@ __attribute__((visibility("default"))) int mdt_lg_run_served(const mdt_lg_req *r
         double t = now_us();
         while (i < n && t0 + reqs[i].t_arrive_us <= t) {
             const mdt_lg_req &q = reqs[i];
+            void *dst = q.fixed;
+            int64_t range = -1;
+            if (q.unpack && !dst && q.span > 0) {
+                int64_t off = 0;
+                range = ring.alloc(q.span, &off);
+                if (range == -2) {
+                    err = MDT_ERR_NO_MEM;
+                    i = n;
+                    break;
+                }
+                if (range < 0) {
+                    const double tw = now_us();
+                    res->ring_waits++;
+                    while ((range = ring.alloc(q.span, &off)) == -1) reap(false);
+                    res->ring_wait_us += now_us() - tw;
+                }
+                dst = ring.base + off;
+            }
             mdt_request r = nullptr;
             int e;
             const double ti = now_us();
             if (q.unpack)
-                e = mdt_server_submit_unpack(srv, q.packed, q.target, const_cast<void *>(q.typed), q.count,
-                                             types[q.type_index], 0, &r);
+                e = mdt_server_submit_unpack(srv, q.packed, q.target, static_cast<uint8_t *>(dst) + q.origin_off,
+                                             q.count, types[q.type_index], 0, &r);
             else
                 e = mdt_server_submit_pack(srv, q.typed, q.count, types[q.type_index], 0, q.target, &r);
             issue.push_back(now_us() - ti);
             if (t - (t0 + q.t_arrive_us) > 50.0) res->late_issues++;
-            if (e) res->failed++;
-            else pend.push_back({r, t0 + q.t_arrive_us, i});
+            if (e) {
+                res->failed++;
+                ring.free(range);
+            } else {
+                pend.push_back({r, t0 + q.t_arrive_us, i, range});
+            }
             i++;
         }
         reap(false);
@@ -183,20 +290,27 @@ __attribute__((visibility("default"))) int mdt_lg_run_served(const mdt_lg_req *r
     res->p50_run_us = st.p50_run_us;
     res->p99_run_us = st.p99_run_us;
     mdt_server_free(&srv);
+    (void)hipStreamDestroy(cs);
     res->elapsed_s = (last_done - t0) * 1e-6;
     summarize(lat, res);
     res->p50_issue_us = pctl(issue, 0.50);
     res->p99_issue_us = pctl(issue, 0.99);
-    return MDT_SUCCESS;
+    return err;
 }
 
-// One plain launch per request on stream (index mod nstreams).
+// One plain launch per request on stream (index mod nstreams); pack outputs
+// and unpack spans come from the ring.
 __attribute__((visibility("default"))) int mdt_lg_run_plain(const mdt_lg_req *reqs, int64_t n, const mdt_type *types,
-                                                            int nstreams, mdt_lg_result *res, double *lat_out)
+                                                            int nstreams, void *ring_base, int64_t ring_bytes,
+                                                            mdt_lg_result *res, double *lat_out)
 {
     std::memset(res, 0, sizeof *res);
     if (lat_out)
         for (int64_t k = 0; k < n; k++) lat_out[k] = -1.0;
+    if (nstreams <= 0 || nstreams > 64) return MDT_ERR_ARG;
+    Ring ring;
+    ring.base = static_cast<uint8_t *>(ring_base);
+    ring.cap = ring_bytes;
     std::vector<hipStream_t> hs((size_t)nstreams);
     std::vector<mdt_stream> ms((size_t)nstreams);
     for (int s = 0; s < nstreams; s++) {
@@ -208,6 +322,7 @@ __attribute__((visibility("default"))) int mdt_lg_run_plain(const mdt_lg_req *re
         double t_arrive;
         int64_t bytes;
         int64_t idx;
+        int64_t range;
     };
     // requests on one stream complete in order: poll only each stream's oldest
     std::vector<std::deque<Pending>> pend((size_t)nstreams);
@@ -218,30 +333,8 @@ __attribute__((visibility("default"))) int mdt_lg_run_plain(const mdt_lg_req *re
     const double t0 = now_us() + 1000.0;
     double last_done = t0;
     int64_t i = 0;
-    while (i < n || npend > 0) {
-        double t = now_us();
-        while (i < n && t0 + reqs[i].t_arrive_us <= t) {
-            const mdt_lg_req &q = reqs[i];
-            mdt_request r = nullptr;
-            int64_t got = 0;
-            mdt_stream s = ms[(size_t)(i % nstreams)];
-            int e;
-            const double ti = now_us();
-            if (q.unpack)
-                e = mdt_unpack_enqueue(q.packed, q.target, const_cast<void *>(q.typed), q.count, types[q.type_index], 0,
-                                       &got, s, &r);
-            else
-                e = mdt_pack_enqueue(q.typed, q.count, types[q.type_index], 0, q.out, q.target, &got, s, &r);
-            issue.push_back(now_us() - ti);
-            if (t - (t0 + q.t_arrive_us) > 50.0) res->late_issues++;
-            if (e) res->failed++;
-            else {
-                pend[(size_t)(i % nstreams)].push_back({r, t0 + q.t_arrive_us, got, i});
-                npend++;
-                res->launches++;
-            }
-            i++;
-        }
+    int err = MDT_SUCCESS;
+    auto reap = [&] {
         for (auto &dq : pend) {
             while (!dq.empty()) {
                 int flag = 0;
@@ -253,10 +346,57 @@ __attribute__((visibility("default"))) int mdt_lg_run_plain(const mdt_lg_req *re
                 lat.push_back(tc - dq.front().t_arrive);
                 if (lat_out) lat_out[dq.front().idx] = tc - dq.front().t_arrive;
                 last_done = std::max(last_done, tc);
+                ring.free(dq.front().range);
                 dq.pop_front();
                 npend--;
             }
         }
+    };
+    while (i < n || npend > 0) {
+        double t = now_us();
+        while (i < n && t0 + reqs[i].t_arrive_us <= t) {
+            const mdt_lg_req &q = reqs[i];
+            void *dst = q.fixed;
+            int64_t range = -1;
+            if (!dst && q.span > 0) {
+                int64_t off = 0;
+                range = ring.alloc(q.span, &off);
+                if (range == -2) {
+                    err = MDT_ERR_NO_MEM;
+                    i = n;
+                    break;
+                }
+                if (range < 0) {
+                    const double tw = now_us();
+                    res->ring_waits++;
+                    while ((range = ring.alloc(q.span, &off)) == -1) reap();
+                    res->ring_wait_us += now_us() - tw;
+                }
+                dst = ring.base + off;
+            }
+            mdt_request r = nullptr;
+            int64_t got = 0;
+            mdt_stream s = ms[(size_t)(i % nstreams)];
+            int e;
+            const double ti = now_us();
+            if (q.unpack)
+                e = mdt_unpack_enqueue(q.packed, q.target, static_cast<uint8_t *>(dst) + q.origin_off, q.count,
+                                       types[q.type_index], 0, &got, s, &r);
+            else
+                e = mdt_pack_enqueue(q.typed, q.count, types[q.type_index], 0, dst, q.target, &got, s, &r);
+            issue.push_back(now_us() - ti);
+            if (t - (t0 + q.t_arrive_us) > 50.0) res->late_issues++;
+            if (e) {
+                res->failed++;
+                ring.free(range);
+            } else {
+                pend[(size_t)(i % nstreams)].push_back({r, t0 + q.t_arrive_us, got, i, range});
+                npend++;
+                res->launches++;
+            }
+            i++;
+        }
+        reap();
         wait_for_next(i < n ? t0 + reqs[i].t_arrive_us : 0.0);
     }
     for (int s = 0; s < nstreams; s++) {
@@ -268,7 +408,7 @@ __attribute__((visibility("default"))) int mdt_lg_run_plain(const mdt_lg_req *re
     summarize(lat, res);
     res->p50_issue_us = pctl(issue, 0.50);
     res->p99_issue_us = pctl(issue, 0.99);
-    return MDT_SUCCESS;
+    return err;
 }
 
 }  // extern "C"
