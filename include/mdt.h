@@ -387,6 +387,35 @@ MDT_API int mdt_grequest_complete(mdt_request req);
 MDT_API int mdt_cancel(mdt_request req);
 
 /* ---------------------------------------------------------------------
+ * General progress (General Progress section: progress invoked on its own,
+ * not through a particular request, per stream, and a progress thread the
+ * caller starts and stops around the phases that need it).
+ *   mdt_stream_progress(s): one progress pass over the requests of work
+ *     enqueued on stream s (mdt_*_enqueue, mdt_batch_launch,
+ *     mdt_type_iov_enqueue with a request): each one whose work has
+ *     finished is recorded as complete, so mdt_request_get_status reports
+ *     it and mdt_test completes it without another runtime query.  s = NULL
+ *     is general progress: every stream's requests and every generalized
+ *     request, whose poll_fn is called (poll_fn is never called by two
+ *     threads at once).  Returns the first error a pass met (a HIP error,
+ *     or a poll_fn's nonzero value); the pass still visits every request.
+ *   mdt_start_progress_thread(s) / mdt_stop_progress_thread(s): a library
+ *     thread making such passes on s (NULL: general progress) back to back
+ *     while some of its requests are incomplete and every 50 us otherwise;
+ *     stop joins it.  Starting a running thread, or stopping a stopped one,
+ *     does nothing.  mdt_stream_free stops the stream's thread; requests of
+ *     a freed stream stay valid for mdt_test / mdt_wait.
+ *   mdt_request_get_status(req, flag): *flag = 1 if req is known to be
+ *     complete (an event request seen finished by a progress pass or a
+ *     test; a generalized request marked by mdt_grequest_complete), without
+ *     invoking progress and without freeing it.  Server requests have their
+ *     own calls (MDT_ERR_ARG). */
+MDT_API int mdt_stream_progress(mdt_stream s);
+MDT_API int mdt_start_progress_thread(mdt_stream s);
+MDT_API int mdt_stop_progress_thread(mdt_stream s);
+MDT_API int mdt_request_get_status(mdt_request req, int *flag);
+
+/* ---------------------------------------------------------------------
  * Batches: many pack/unpack requests of mixed types and sizes executed by
  * one kernel launch per direction (pack requests and copies first, then
  * unpack requests).  How that launch runs is the batch's configuration
@@ -468,6 +497,7 @@ typedef struct mdt_server_stats {
     mdt_count inflight_bytes, peak_inflight_bytes;
     double p50_queue_us, p99_queue_us; /* submission -> launch */
     double p50_run_us, p99_run_us;     /* launch -> completion seen by the progress engine */
+    mdt_count direct;          /* requests launched by their own submit (nothing queued, a slot free) */
 } mdt_server_stats;
 MDT_API int mdt_server_create(const mdt_server_config *cfg, mdt_server *out);
 /* Drains every admitted request, stops the progress thread, frees the

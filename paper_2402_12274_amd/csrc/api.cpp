@@ -52,7 +52,7 @@ void event_put(hipEvent_t ev)
     g_events.free.push_back(ev);
 }
 
-int request_from_stream(hipStream_t s, mdt_request *req)
+int request_from_stream(hipStream_t s, mdt_request *req, mdt_stream owner)
 {
     if (!req) return MDT_SUCCESS;
     auto *r = new (std::nothrow) mdt_request_s();
@@ -70,6 +70,7 @@ int request_from_stream(hipStream_t s, mdt_request *req)
         return MDT_ERR_HIP;
     }
     r->kind = REQ_EVENT;
+    if (owner) list_add(&owner->live, r);  // reachable by the stream's progress
     *req = r;
     return MDT_SUCCESS;
 }
@@ -97,7 +98,7 @@ int prepare(mdt_type th, int64_t count, Compiled **C, DeviceTables **D, int64_t 
 }
 
 int pack_common(const void *inbuf, int64_t incount, mdt_type t, int64_t inoffset, void *outbuf, int64_t max_bytes,
-                int64_t *actual, hipStream_t s, mdt_request *req)
+                int64_t *actual, hipStream_t s, mdt_request *req, mdt_stream owner = nullptr)
 {
     if (!actual || inoffset < 0 || max_bytes < -1) return MDT_ERR_ARG;
     Compiled *C;
@@ -114,14 +115,14 @@ int pack_common(const void *inbuf, int64_t incount, mdt_type t, int64_t inoffset
         rc = launch_xfer(D->lay, A, false, s);
         if (rc) return rc;
     }
-    rc = request_from_stream(s, req);
+    rc = request_from_stream(s, req, owner);
     if (rc) return rc;
     *actual = n;
     return MDT_SUCCESS;
 }
 
 int unpack_common(const void *inbuf, int64_t insize, void *outbuf, int64_t outcount, mdt_type t, int64_t outoffset,
-                  int64_t *actual, hipStream_t s, mdt_request *req)
+                  int64_t *actual, hipStream_t s, mdt_request *req, mdt_stream owner = nullptr)
 {
     if (!actual || insize < 0 || outoffset < 0) return MDT_ERR_ARG;
     Compiled *C;
@@ -140,14 +141,15 @@ int unpack_common(const void *inbuf, int64_t insize, void *outbuf, int64_t outco
         rc = launch_xfer(D->lay, A, true, s);
         if (rc) return rc;
     }
-    rc = request_from_stream(s, req);
+    rc = request_from_stream(s, req, owner);
     if (rc) return rc;
     *actual = insize;
     return MDT_SUCCESS;
 }
 
 int copy_common(const void *src, int64_t srccount, mdt_type srctype, void *dst, int64_t dstcount, mdt_type dsttype,
-                int64_t offset, int64_t max_bytes, int64_t *actual, hipStream_t s, mdt_request *req)
+                int64_t offset, int64_t max_bytes, int64_t *actual, hipStream_t s, mdt_request *req,
+                mdt_stream owner = nullptr)
 {
     if (!actual || offset < 0 || max_bytes < -1) return MDT_ERR_ARG;
     Compiled *Cs, *Cd;
@@ -183,7 +185,7 @@ int copy_common(const void *src, int64_t srccount, mdt_type srctype, void *dst, 
         rc = launch_copy(Ds->lay, Dd->lay, A, s);
         if (rc) return rc;
     }
-    rc = request_from_stream(s, req);
+    rc = request_from_stream(s, req, owner);
     if (rc) return rc;
     *actual = n;
     return MDT_SUCCESS;
@@ -191,6 +193,7 @@ int copy_common(const void *src, int64_t srccount, mdt_type srctype, void *dst, 
 
 void free_request(mdt_request r)
 {
+    if (r->list) list_remove(r);
     if (r->kind == REQ_EVENT) event_put(r->ev);
     r->magic = 0;
     delete r;
@@ -259,6 +262,7 @@ MDT_API int mdt_stream_create(mdt_hip_stream s, mdt_stream *out)
     if (!st) return MDT_ERR_NO_MEM;
     st->magic = STREAM_MAGIC;
     st->s = reinterpret_cast<hipStream_t>(s);
+    streams_register(st);
     *out = st;
     return MDT_SUCCESS;
 }
@@ -266,8 +270,21 @@ MDT_API int mdt_stream_create(mdt_hip_stream s, mdt_stream *out)
 MDT_API int mdt_stream_free(mdt_stream *s)
 {
     if (!s || !valid_stream(*s)) return MDT_ERR_ARG;
-    (*s)->magic = 0;
-    delete *s;
+    mdt_stream st = *s;
+    mdt_stop_progress_thread(st);
+    streams_unregister(st);  // no general progress pass reaches it from here on
+    // its requests stay valid (completed by test or wait); they leave its list
+    for (;;) {
+        mdt_request r;
+        {
+            std::lock_guard<std::mutex> g(st->live.mu);
+            r = st->live.head;
+        }
+        if (!r) break;
+        list_remove(r);
+    }
+    st->magic = 0;
+    delete st;
     *s = nullptr;
     return MDT_SUCCESS;
 }
@@ -277,7 +294,7 @@ MDT_API int mdt_pack_enqueue(const void *inbuf, mdt_count incount, mdt_type t, m
                              mdt_stream s, mdt_request *req)
 {
     if (!valid_stream(s)) return MDT_ERR_ARG;
-    return pack_common(inbuf, incount, t, inoffset, outbuf, max_pack_bytes, actual_pack_bytes, s->s, req);
+    return pack_common(inbuf, incount, t, inoffset, outbuf, max_pack_bytes, actual_pack_bytes, s->s, req, s);
 }
 
 MDT_API int mdt_unpack_enqueue(const void *inbuf, mdt_count insize, void *outbuf, mdt_count outcount,
@@ -285,7 +302,7 @@ MDT_API int mdt_unpack_enqueue(const void *inbuf, mdt_count insize, void *outbuf
                                mdt_stream s, mdt_request *req)
 {
     if (!valid_stream(s)) return MDT_ERR_ARG;
-    return unpack_common(inbuf, insize, outbuf, outcount, t, outoffset, actual_unpack_bytes, s->s, req);
+    return unpack_common(inbuf, insize, outbuf, outcount, t, outoffset, actual_unpack_bytes, s->s, req, s);
 }
 
 MDT_API int mdt_typed_copy_enqueue(const void *src, mdt_count srccount, mdt_type srctype, void *dst,
@@ -293,7 +310,7 @@ MDT_API int mdt_typed_copy_enqueue(const void *src, mdt_count srccount, mdt_type
                                    mdt_count *actual, mdt_stream s, mdt_request *req)
 {
     if (!valid_stream(s)) return MDT_ERR_ARG;
-    return copy_common(src, srccount, srctype, dst, dstcount, dsttype, offset, max_bytes, actual, s->s, req);
+    return copy_common(src, srccount, srctype, dst, dstcount, dsttype, offset, max_bytes, actual, s->s, req, s);
 }
 
 MDT_API int mdt_type_iov_enqueue(mdt_type t, mdt_count iov_offset, mdt_iov *dev_iov, mdt_count max_iov_len,
@@ -315,7 +332,7 @@ MDT_API int mdt_type_iov_enqueue(mdt_type t, mdt_count iov_offset, mdt_iov *dev_
     int64_t m = iov_offset >= nseg ? 0 : std::min<int64_t>(max_iov_len, nseg - iov_offset);
     rc = launch_flatten(C, D, iov_offset, m, dev_iov, base, s->s);
     if (rc) return rc;
-    rc = request_from_stream(s->s, req);
+    rc = request_from_stream(s->s, req, s);
     if (rc) return rc;
     *actual_iov_len = m;
     return MDT_SUCCESS;

@@ -680,7 +680,7 @@ MDT_API int mdt_batch_launch(mdt_batch b, mdt_stream s, mdt_request *req)
     if (!valid_batch(b) || !s || s->magic != STREAM_MAGIC) return MDT_ERR_ARG;
     int rc = launch(b, s->s);
     if (rc) return rc;
-    return request_from_stream(s->s, req);
+    return request_from_stream(s->s, req, s);
 }
 
 MDT_API int mdt_batch_autotune(mdt_batch b, mdt_stream s, mdt_batch_config *best)

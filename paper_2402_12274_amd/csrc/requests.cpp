@@ -5,9 +5,21 @@
 // library's own test and wait calls with no progress thread of the caller's,
 // and a wait callback that blocks on many of the caller's tasks at once
 // instead of polling each one.
+//
+// General progress (General Progress section: a progress call not tied to a
+// request, per stream, and a progress thread the caller starts and stops):
+// mdt_stream_progress(s) looks at the requests of work enqueued on stream s
+// and records those whose work has finished; with no stream it also polls
+// every generalized request (its poll_fn), so tasks complete in the
+// background.  mdt_start_progress_thread(s) runs such passes on a thread of
+// the library until mdt_stop_progress_thread(s): busy while requests are
+// incomplete, sleeping in short naps while there are none.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <vector>
@@ -24,7 +36,84 @@ struct GRequest {
     mdt_grequest_wait_fn wait_fn;
     void *state;
     std::atomic<int> done{0};
+    std::atomic<int> polling{0};  // a thread is inside poll_fn (polls never run concurrently)
 };
+
+// ---- progress lists ------------------------------------------------------
+
+void list_add(ReqList *l, mdt_request r)
+{
+    std::lock_guard<std::mutex> g(l->mu);
+    r->list = l;
+    r->prev = nullptr;
+    r->next = l->head;
+    if (l->head) l->head->prev = r;
+    l->head = r;
+    l->count.fetch_add(1, std::memory_order_relaxed);
+}
+
+void list_remove(mdt_request r)
+{
+    ReqList *l = r->list;
+    if (!l) return;
+    {
+        std::lock_guard<std::mutex> g(l->mu);
+        if (r->prev) r->prev->next = r->next;
+        else l->head = r->next;
+        if (r->next) r->next->prev = r->prev;
+        r->prev = r->next = nullptr;
+        r->list = nullptr;
+        l->count.fetch_sub(1, std::memory_order_relaxed);
+    }
+    // a progress pass that pinned r before it left the list still uses it
+    while (r->pins.load(std::memory_order_acquire) != 0) std::this_thread::yield();
+}
+
+namespace {
+
+ReqList g_general;  // generalized requests (reached by general progress)
+
+struct StreamRegistry {
+    std::mutex mu;
+    std::vector<mdt_stream> all;
+} g_streams;
+
+struct GeneralThread {
+    std::mutex mu;  // start / stop
+    std::atomic<bool> run{false};
+    std::thread th;
+} g_thread;
+
+// Pin the members of a list (under its lock) so they can be used after it
+// is released; unpin when done.
+void snapshot(ReqList *l, std::vector<mdt_request> *out)
+{
+    std::lock_guard<std::mutex> g(l->mu);
+    for (mdt_request r = l->head; r; r = r->next) {
+        r->pins.fetch_add(1, std::memory_order_acq_rel);
+        out->push_back(r);
+    }
+}
+
+void unpin(const std::vector<mdt_request> &v)
+{
+    for (mdt_request r : v) r->pins.fetch_sub(1, std::memory_order_acq_rel);
+}
+
+}  // namespace
+
+void streams_register(mdt_stream s)
+{
+    std::lock_guard<std::mutex> g(g_streams.mu);
+    g_streams.all.push_back(s);
+}
+
+void streams_unregister(mdt_stream s)
+{
+    std::lock_guard<std::mutex> g(g_streams.mu);
+    auto it = std::find(g_streams.all.begin(), g_streams.all.end(), s);
+    if (it != g_streams.all.end()) g_streams.all.erase(it);
+}
 
 static bool valid_req(mdt_request r) { return r && r->magic == REQUEST_MAGIC; }
 
@@ -41,6 +130,7 @@ static int finish(mdt_request *req)
 {
     mdt_request r = *req;
     int rc = MDT_SUCCESS;
+    list_remove(r);  // first: a progress pass may still hold it
     if (r->kind == REQ_GENERAL) {
         GRequest *g = static_cast<GRequest *>(r->general);
         int q = g->query_fn ? g->query_fn(g->state) : 0;
@@ -63,6 +153,83 @@ static int sync_event(mdt_request r)
         return MDT_ERR_HIP;
     }
     return MDT_SUCCESS;
+}
+
+// Call a generalized request's poll_fn unless it is done, has none, or
+// another thread is polling it right now.
+static int poll_once(GRequest *g)
+{
+    if (general_done(g) || !g->poll_fn) return MDT_SUCCESS;
+    if (g->polling.exchange(1, std::memory_order_acq_rel)) return MDT_SUCCESS;
+    int rc = general_done(g) ? MDT_SUCCESS : g->poll_fn(g->state);
+    g->polling.store(0, std::memory_order_release);
+    return rc;
+}
+
+// One progress pass over stream s (NULL: every stream, then the generalized
+// requests).  *open counts the requests it found incomplete.
+static int progress_pass(mdt_stream s, int64_t *open)
+{
+    std::vector<mdt_stream> streams;
+    if (s) {
+        streams.push_back(s);
+    } else {
+        std::lock_guard<std::mutex> g(g_streams.mu);
+        streams = g_streams.all;
+    }
+    int first = MDT_SUCCESS;
+    std::vector<mdt_request> v;
+    for (mdt_stream st : streams) {
+        if (!s) {
+            // a stream freed meanwhile has left the registry before its
+            // requests leave its list
+            std::lock_guard<std::mutex> g(g_streams.mu);
+            if (std::find(g_streams.all.begin(), g_streams.all.end(), st) == g_streams.all.end()) continue;
+            if (st->live.count.load(std::memory_order_relaxed) == 0) continue;
+            snapshot(&st->live, &v);
+        } else {
+            snapshot(&st->live, &v);
+        }
+        for (mdt_request r : v) {
+            if (r->done.load(std::memory_order_acquire)) continue;
+            hipError_t e = hipEventQuery(r->ev);
+            if (e == hipSuccess) {
+                r->done.store(1, std::memory_order_release);
+            } else {
+                ++*open;
+                if (e != hipErrorNotReady && !first) {
+                    set_hip_error((int)e);
+                    first = MDT_ERR_HIP;
+                }
+            }
+        }
+        unpin(v);
+        v.clear();
+    }
+    if (!s && g_general.count.load(std::memory_order_relaxed) > 0) {
+        snapshot(&g_general, &v);
+        for (mdt_request r : v) {
+            GRequest *g = static_cast<GRequest *>(r->general);
+            int rc = poll_once(g);
+            if (rc && !first) first = rc;
+            if (!general_done(g)) ++*open;
+        }
+        unpin(v);
+    }
+    return first;
+}
+
+// The progress thread: passes back to back while requests are incomplete,
+// 50 us naps while there are none.
+static void progress_loop(std::atomic<bool> *run, mdt_stream s, int device)
+{
+    if (device >= 0) (void)hipSetDevice(device);
+    while (run->load(std::memory_order_acquire)) {
+        int64_t open = 0;
+        (void)progress_pass(s, &open);
+        if (open == 0) std::this_thread::sleep_for(std::chrono::microseconds(50));
+        else std::this_thread::yield();
+    }
 }
 
 // Drive the incomplete generalized requests among reqs[0..n) until all are
@@ -105,7 +272,7 @@ static int drive_general(int n, const mdt_request *reqs)
         }
         for (GRequest *g : open) {
             if (g->wait_fn || !g->poll_fn || general_done(g)) continue;
-            int rc = g->poll_fn(g->state);
+            int rc = poll_once(g);
             if (rc) return rc;
             progress = progress || general_done(g);
         }
@@ -139,6 +306,7 @@ MDT_API int mdt_grequest_start(mdt_grequest_query_fn query_fn, mdt_grequest_free
     g->state = extra_state;
     r->kind = REQ_GENERAL;
     r->general = g;
+    list_add(&g_general, r);  // reachable by general progress
     *req = r;
     return MDT_SUCCESS;
 }
@@ -181,18 +349,19 @@ MDT_API int mdt_test(mdt_request *req, int *flag)
     if (!valid_req(r) || r->kind == REQ_SERVER) return MDT_ERR_ARG;
     bool done;
     if (r->kind == REQ_EVENT) {
-        hipError_t e = hipEventQuery(r->ev);
-        if (e != hipSuccess && e != hipErrorNotReady) {
-            set_hip_error((int)e);
-            return MDT_ERR_HIP;
+        done = r->done.load(std::memory_order_acquire) != 0;  // seen by a progress pass
+        if (!done) {
+            hipError_t e = hipEventQuery(r->ev);
+            if (e != hipSuccess && e != hipErrorNotReady) {
+                set_hip_error((int)e);
+                return MDT_ERR_HIP;
+            }
+            done = e == hipSuccess;
         }
-        done = e == hipSuccess;
     } else {
         GRequest *g = static_cast<GRequest *>(r->general);
-        if (!general_done(g) && g->poll_fn) {
-            int rc = g->poll_fn(g->state);
-            if (rc) return rc;
-        }
+        int rc = poll_once(g);
+        if (rc) return rc;
         done = general_done(g);
     }
     if (!done) {
@@ -224,6 +393,55 @@ MDT_API int mdt_waitall(int n, mdt_request reqs[])
         if (f && !first) first = f;
     }
     return first;
+}
+
+MDT_API int mdt_stream_progress(mdt_stream s)
+{
+    if (s && s->magic != STREAM_MAGIC) return MDT_ERR_ARG;
+    int64_t open = 0;
+    return progress_pass(s, &open);
+}
+
+MDT_API int mdt_start_progress_thread(mdt_stream s)
+{
+    if (s && s->magic != STREAM_MAGIC) return MDT_ERR_ARG;
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> g(g_thread.mu);
+    std::atomic<bool> *run = s ? &s->run : &g_thread.run;
+    std::thread *th = s ? &s->th : &g_thread.th;
+    if (run->exchange(true)) return MDT_SUCCESS;  // already running
+    try {
+        *th = std::thread(progress_loop, run, s, dev);
+    } catch (...) {
+        run->store(false);
+        return MDT_ERR_NO_MEM;
+    }
+    return MDT_SUCCESS;
+}
+
+MDT_API int mdt_stop_progress_thread(mdt_stream s)
+{
+    if (s && s->magic != STREAM_MAGIC) return MDT_ERR_ARG;
+    std::lock_guard<std::mutex> g(g_thread.mu);
+    std::atomic<bool> *run = s ? &s->run : &g_thread.run;
+    std::thread *th = s ? &s->th : &g_thread.th;
+    if (!run->exchange(false)) return MDT_SUCCESS;
+    if (th->joinable()) th->join();
+    return MDT_SUCCESS;
+}
+
+MDT_API int mdt_request_get_status(mdt_request req, int *flag)
+{
+    if (!flag) return MDT_ERR_ARG;
+    if (req == MDT_REQUEST_NULL) {
+        *flag = 1;
+        return MDT_SUCCESS;
+    }
+    if (!valid_req(req) || req->kind == REQ_SERVER) return MDT_ERR_ARG;
+    *flag = req->kind == REQ_EVENT ? req->done.load(std::memory_order_acquire) != 0
+                                   : general_done(static_cast<GRequest *>(req->general));
+    return MDT_SUCCESS;
 }
 
 }  // extern "C"

@@ -18,11 +18,15 @@
 //      not held behind a large one) into one launch on the stream with the
 //      least work in flight: a lone request with the single-request kernels,
 //      several as one batched launch; record its completion event.
-// A submit runs a round itself, so a request that can be admitted is
-// launched before submit returns; requests that arrive while others run are
-// admitted as soon as slots and memory free up, and their work overlaps on
-// the device.  Each request's bytes are those of the same request run alone
-// (the batch runs the single-request tile bodies).
+// A submit that finds nothing waiting and a launch slot free admits and
+// launches its own request directly (one lock, the single-request kernels,
+// as a plain enqueue); otherwise it queues, and the progress thread cuts
+// whatever has queued into batched launches.  Requests that arrive while
+// others run are admitted as soon as slots and memory free up, and their
+// work overlaps on the device.  Clients testing their requests query their
+// own launch's event; the progress thread then stays out of the HIP runtime
+// except to launch queued work.  Each request's bytes are those of the same
+// request run alone (the batch runs the single-request tile bodies).
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -43,10 +47,6 @@
 
 namespace mdt {
 int batch_launch_internal(mdt_batch b, hipStream_t s);
-int pack_common(const void *inbuf, int64_t incount, mdt_type t, int64_t inoffset, void *outbuf, int64_t max_bytes,
-                int64_t *actual, hipStream_t s, mdt_request *req);
-int unpack_common(const void *inbuf, int64_t insize, void *outbuf, int64_t outcount, mdt_type t, int64_t outoffset,
-                  int64_t *actual, hipStream_t s, mdt_request *req);
 }
 
 using namespace mdt;
@@ -85,7 +85,27 @@ constexpr double SPIN_US = 2000.0;
 // that only need completing at a slower cadence (so it rarely contends with
 // clients for the runtime).
 constexpr double TEST_REAP_US = 1.0;
-constexpr double THREAD_REAP_US = 20.0;
+const double THREAD_REAP_US = [] {
+    const char *e = getenv("MDT_SERVER_THREAD_REAP_US");
+    double v = e && *e ? atof(e) : 20.0;
+    return v > 0 ? v : 20.0;
+}();
+// While clients test their own requests (each test queries its launch's
+// event, as a plain enqueue's caller would), the progress thread leaves
+// completion to them and stays out of the HIP runtime: it reaps only when
+// no client has tested for this long.
+const double CLIENT_QUIET_US = [] {
+    const char *e = getenv("MDT_SERVER_CLIENT_QUIET_US");
+    double v = e && *e ? atof(e) : 200.0;
+    return v >= 0 ? v : 200.0;
+}();
+// A submit that finds nothing queued and a launch slot free launches its
+// request itself, with no queue round trip (MDT_SERVER_DIRECT=0 turns the
+// direct path off: every request then goes through a progress round).
+const bool DIRECT = [] {
+    const char *e = getenv("MDT_SERVER_DIRECT");
+    return !(e && *e == '0');
+}();
 
 double now_us()
 {
@@ -96,6 +116,7 @@ double now_us()
 struct Item {
     int unpack = 0;
     TypeNode *type = nullptr;  // retained
+    DeviceTables *dt = nullptr;  // the type's resident tables on the server's device
     const void *in = nullptr;
     void *out = nullptr;
     int64_t count = 0, off = 0, nbytes = 0;
@@ -219,6 +240,8 @@ struct mdt_server_s {
     std::atomic<int64_t> work{0};   // queued + admitted items + launches in flight
     std::atomic<int> launches_inflight{0};
     std::atomic<double> last_reap{0.0};  // time of the last completion query round
+    std::atomic<double> last_client_test{0.0};  // time of the last client test of a launched request
+    int64_t direct = 0;          // requests launched by their own submit (direct path)
     std::condition_variable wake;  // submit -> idle progress thread
     std::thread th;
     // stats
@@ -338,6 +361,74 @@ bool reap_unlocked(mdt_server s)
     return true;
 }
 
+// The stream a launch goes to: one with a free slot whose hardware queue
+// has the least work queued ahead of it (streams are spread over the
+// process's hardware queues in creation order, so streams i and i + k*HWQ
+// share one, and its work runs in order).  Large requests take hardware
+// queue 0 in arrival order (two large requests then finish one after the
+// other instead of both late); the others use the remaining queues.
+// Caller holds s->mu.  NULL when no suitable slot is free.
+StreamState *pick_stream(mdt_server s, bool large)
+{
+    const int nst = (int)s->streams.size();
+    const int hwq = std::max(1, std::min(nst, HW_QUEUES));
+    int64_t qbytes[64] = {0};
+    for (int i = 0; i < nst; i++) qbytes[i % hwq] += s->streams[(size_t)i].bytes;
+    StreamState *best = nullptr;
+    int64_t best_load = 0;
+    for (int i = 0; i < nst; i++) {
+        StreamState &st = s->streams[(size_t)i];
+        if (st.busy >= (int)st.slots.size()) continue;
+        if (hwq > 1 && (i % hwq == 0) != large) continue;
+        const int64_t load = qbytes[i % hwq];
+        if (!best || load < best_load || (load == best_load && st.busy < best->busy)) {
+            best = &st;
+            best_load = load;
+        }
+    }
+    return best;
+}
+
+Slot *free_slot(StreamState &st)
+{
+    for (auto &x : st.slots)
+        if (!x.busy) return &x;
+    return nullptr;
+}
+
+// Launch one request with the single-request kernels (no descriptor
+// upload) on stream `st`, slot `sl`, and record the slot's event.  Caller
+// holds s->mu.  On failure the request is completed with the error.
+int launch_single(mdt_server s, Item *it, StreamState *st, Slot *sl)
+{
+    int r = MDT_SUCCESS;
+    if (it->nbytes > 0) {
+        XferArgs A = it->unpack ? make_args(it->out, const_cast<void *>(it->in), it->off, it->nbytes)
+                                : make_args(it->in, it->out, it->off, it->nbytes);
+        r = launch_xfer(it->dt->lay, A, it->unpack != 0, st->s);
+    }
+    hipError_t e = r == MDT_SUCCESS ? hipEventRecord(sl->ev, st->s) : hipErrorUnknown;
+    if (r != MDT_SUCCESS || e != hipSuccess) {
+        if (r == MDT_SUCCESS) set_hip_error((int)e);
+        complete(s, it, r ? r : MDT_ERR_HIP, now_us());
+        return r ? r : MDT_ERR_HIP;
+    }
+    sl->items.push_back(it);
+    sl->busy = true;
+    sl->seq = st->next_seq++;
+    it->st = st;
+    it->slot = sl;
+    it->seq = sl->seq;
+    it->t_launch = now_us();
+    it->state.store(2, std::memory_order_release);
+    sl->bytes = it->nbytes;
+    st->busy++;
+    st->bytes += sl->bytes;
+    s->launches++;
+    s->launches_inflight.fetch_add(1, std::memory_order_relaxed);
+    return MDT_SUCCESS;
+}
+
 // Admit and launch; caller holds s->mu.
 int progress_locked(mdt_server s)
 {
@@ -391,30 +482,9 @@ int progress_locked(mdt_server s)
     }
     // 3. launch batches on free slots, least-loaded stream first
     while (!s->admitted.empty()) {
-        // the stream with a free slot and the least work queued ahead of it
-        // on its hardware queue (streams are spread over the process's
-        // hardware queues in creation order, so streams i and i + k*HWQ share
-        // one, and its work runs in order)
-        const int nst = (int)s->streams.size();
-        const int hwq = std::max(1, std::min(nst, HW_QUEUES));
-        int64_t qbytes[64] = {0};
-        for (int i = 0; i < nst; i++) qbytes[i % hwq] += s->streams[(size_t)i].bytes;
-        // large requests take hardware queue 0 in arrival order (two large
-        // requests then finish one after the other instead of both late);
-        // the others use the remaining queues
         const bool large = s->admitted.front()->nbytes >= LARGE_BYTES;
-        StreamState *best = nullptr;
-        int64_t best_load = 0;
-        for (int i = 0; i < nst; i++) {
-            StreamState &st = s->streams[(size_t)i];
-            if (st.busy >= (int)st.slots.size()) continue;
-            if (hwq > 1 && (i % hwq == 0) != large) continue;
-            const int64_t load = qbytes[i % hwq];
-            if (!best || load < best_load || (load == best_load && st.busy < best->busy)) {
-                best = &st;
-                best_load = load;
-            }
-        }
+        const int hwq = std::max(1, std::min((int)s->streams.size(), HW_QUEUES));
+        StreamState *best = pick_stream(s, large);
         if (!best) {
             // the large queue is full: let a small request behind go first
             auto it = std::find_if(s->admitted.begin(), s->admitted.end(),
@@ -425,12 +495,7 @@ int progress_locked(mdt_server s)
             s->admitted.push_front(x);
             continue;
         }
-        Slot *sl = nullptr;
-        for (auto &x : best->slots)
-            if (!x.busy) {
-                sl = &x;
-                break;
-            }
+        Slot *sl = free_slot(*best);
         // a lone request is launched with the single-request kernels (no
         // descriptor upload); several go through one batched launch
         size_t take_n = 0;
@@ -445,29 +510,8 @@ int progress_locked(mdt_server s)
         if (take_n == 1) {
             Item *it = s->admitted.front();
             s->admitted.pop_front();
-            int64_t got = 0;
-            mdt_type th = reinterpret_cast<mdt_type>(it->type);
-            int r = it->unpack ? unpack_common(it->in, it->nbytes, it->out, it->count, th, it->off, &got, best->s, nullptr)
-                               : pack_common(it->in, it->count, th, it->off, it->out, it->nbytes, &got, best->s, nullptr);
-            hipError_t e = r == MDT_SUCCESS ? hipEventRecord(sl->ev, best->s) : hipErrorUnknown;
-            if (r != MDT_SUCCESS || e != hipSuccess) {
-                complete(s, it, r ? r : MDT_ERR_HIP, now_us());
-                rc = r ? r : MDT_ERR_HIP;
-                continue;
-            }
-            sl->items.push_back(it);
-            sl->busy = true;
-            sl->seq = best->next_seq++;
-            it->st = best;
-            it->slot = sl;
-            it->seq = sl->seq;
-            it->t_launch = now_us();
-            it->state.store(2, std::memory_order_release);
-            sl->bytes = it->nbytes;
-            best->busy++;
-            best->bytes += sl->bytes;
-            s->launches++;
-            s->launches_inflight.fetch_add(1, std::memory_order_relaxed);
+            int r = launch_single(s, it, best, sl);
+            if (r) rc = r;
             continue;
         }
         mdt_batch_clear(sl->batch);
@@ -560,7 +604,8 @@ void thread_main(mdt_server s)
         }
         const double t = now_us();
         if (nl > 0) {
-            if (t - s->last_reap.load(std::memory_order_relaxed) >= THREAD_REAP_US && reap_unlocked(s)) {
+            if (t - s->last_reap.load(std::memory_order_relaxed) >= THREAD_REAP_US &&
+                t - s->last_client_test.load(std::memory_order_relaxed) >= CLIENT_QUIET_US && reap_unlocked(s)) {
                 std::lock_guard<std::mutex> g(s->mu);
                 progress_locked(s);
             }
@@ -585,6 +630,50 @@ bool idle_all(mdt_server s)
     return true;
 }
 
+// Direct path: with nothing queued or admitted ahead of it and a launch
+// slot free, the submitter admits and launches its own request under one
+// lock (as a plain enqueue launches), without a queue round trip or a full
+// progress round.  Returns false when the request has to queue instead
+// (requests waiting, no free slot, budget or arena exhausted); nothing has
+// changed then.
+bool try_direct(mdt_server s, Item *it)
+{
+    if (s->work.load(std::memory_order_acquire) != (int64_t)s->launches_inflight.load(std::memory_order_relaxed))
+        return false;
+    std::lock_guard<std::mutex> g(s->mu);
+    if (!s->admitted.empty()) return false;
+    {
+        std::lock_guard<std::mutex> q(s->qmu);
+        if (!s->queue.empty()) return false;
+        take_back_released(s);
+    }
+    if (s->inflight + it->charge > s->cfg.budget_bytes && s->inflight > 0) return false;
+    if (!it->unpack && s->inject_fail > 0) return false;  // the queued path reports injected failures
+    StreamState *st = pick_stream(s, it->nbytes >= LARGE_BYTES);
+    if (!st) return false;
+    if (!it->unpack) {
+        const int64_t off = s->arena.alloc(std::max<int64_t>(it->nbytes, 1));
+        if (off < 0) return false;
+        it->arena_off = off;
+        it->packed = s->arena.base + off;
+        it->out = it->packed;
+    }
+    s->inflight += it->charge;
+    s->peak_inflight = std::max(s->peak_inflight, s->inflight);
+    it->state.store(1, std::memory_order_release);
+    {
+        std::lock_guard<std::mutex> q(s->qmu);
+        s->submitted++;
+        if (s->first_submit < 0) s->first_submit = it->t_submit;
+    }
+    s->direct++;
+    if (launch_single(s, it, st, free_slot(*st)) == MDT_SUCCESS) {
+        std::lock_guard<std::mutex> q(s->qmu);
+        s->work.fetch_add(1, std::memory_order_release);
+    }
+    return true;
+}
+
 int submit(mdt_server s, Item *it, mdt_request *req)
 {
     auto *r = new (std::nothrow) mdt_request_s();
@@ -604,6 +693,10 @@ int submit(mdt_server s, Item *it, mdt_request *req)
     // the progress thread cuts whatever has queued into batched launches,
     // which keeps the cost per submit low and the launches few.
     const bool thread = s->run_thread.load(std::memory_order_acquire);
+    if (DIRECT && thread && try_direct(s, it)) {
+        *req = r;
+        return MDT_SUCCESS;
+    }
     const int nl = s->launches_inflight.load(std::memory_order_relaxed);
     const bool waiting = s->work.load(std::memory_order_acquire) > (int64_t)nl;
     auto enqueue = [&] {
@@ -663,9 +756,9 @@ MDT_API int mdt_server_create(const mdt_server_config *cfg, mdt_server *out)
         return MDT_ERR_NO_MEM;
     }
     s->arena.init(s->arena.base, c.arena_bytes);
-    s->lat_us.reserve(1 << 20);
-    s->queue_us.reserve(1 << 20);
-    s->run_us.reserve(1 << 20);
+    s->lat_us.reserve(1 << 22);
+    s->queue_us.reserve(1 << 22);
+    s->run_us.reserve(1 << 22);
     s->streams.resize(c.nstreams);
     int rc = MDT_SUCCESS;
     for (auto &st : s->streams) {
@@ -725,8 +818,9 @@ MDT_API int mdt_server_submit_pack(mdt_server srv, const void *inbuf, mdt_count 
 {
     if (!valid_server(srv) || !req || inoffset < 0 || max_pack_bytes < -1) return MDT_ERR_ARG;
     Compiled *C;
+    DeviceTables *D;
     int64_t total;
-    int rc = prepare(t, incount, &C, nullptr, &total);
+    int rc = prepare(t, incount, &C, &D, &total);
     if (rc) return rc;
     int64_t n = std::max<int64_t>(0, total - inoffset);
     if (max_pack_bytes >= 0) n = std::min<int64_t>(n, max_pack_bytes);
@@ -736,6 +830,7 @@ MDT_API int mdt_server_submit_pack(mdt_server srv, const void *inbuf, mdt_count 
     if (!it) return MDT_ERR_NO_MEM;
     it->unpack = 0;
     it->type = reinterpret_cast<TypeNode *>(t);
+    it->dt = D;
     retain(it->type);
     it->in = inbuf;
     it->count = incount;
@@ -750,8 +845,9 @@ MDT_API int mdt_server_submit_unpack(mdt_server srv, const void *inbuf, mdt_coun
 {
     if (!valid_server(srv) || !req || insize < 0 || outoffset < 0) return MDT_ERR_ARG;
     Compiled *C;
+    DeviceTables *D;
     int64_t total;
-    int rc = prepare(t, outcount, &C, nullptr, &total);
+    int rc = prepare(t, outcount, &C, &D, &total);
     if (rc) return rc;
     if (insize > std::max<int64_t>(0, total - outoffset)) return MDT_ERR_TRUNCATE;
     rc = check_unpack_overlap(C, outcount);
@@ -762,6 +858,7 @@ MDT_API int mdt_server_submit_unpack(mdt_server srv, const void *inbuf, mdt_coun
     if (!it) return MDT_ERR_NO_MEM;
     it->unpack = 1;
     it->type = tn;
+    it->dt = D;
     retain(tn);
     it->in = inbuf;
     it->out = outbuf;
@@ -779,6 +876,7 @@ MDT_API int mdt_server_request_test(mdt_server srv, mdt_request req, int *flag)
     Item *it = item_of(req);
     if (!valid_server(srv) || !it || !flag) return MDT_ERR_ARG;
     const int st = it->state.load(std::memory_order_acquire);
+    if (st == 2) srv->last_client_test.store(now_us(), std::memory_order_relaxed);
     if (st == 2 && srv->run_thread.load()) {
         // the client queries the event of its own launch only (as the caller
         // of a plain enqueue queries its own event); once it has finished,
@@ -919,6 +1017,7 @@ MDT_API int mdt_server_stats_get(mdt_server srv, mdt_server_stats *out)
     out->p99_queue_us = pct(srv->queue_us, 0.99);
     out->p50_run_us = pct(srv->run_us, 0.50);
     out->p99_run_us = pct(srv->run_us, 0.99);
+    out->direct = srv->direct;
     return MDT_SUCCESS;
 }
 

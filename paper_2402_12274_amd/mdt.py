@@ -74,7 +74,7 @@ class ServerStats(C.Structure):
                 ("p50_us", C.c_double), ("p99_us", C.c_double), ("max_us", C.c_double),
                 ("elapsed_s", C.c_double), ("inflight_bytes", C.c_int64), ("peak_inflight_bytes", C.c_int64),
                 ("p50_queue_us", C.c_double), ("p99_queue_us", C.c_double), ("p50_run_us", C.c_double),
-                ("p99_run_us", C.c_double)]
+                ("p99_run_us", C.c_double), ("direct", C.c_int64)]
 
 
 # generalized-request callbacks (include/mdt.h)
@@ -125,6 +125,10 @@ _SIGS = {
                             C.POINTER(_P)], _INT),
     "mdt_grequest_complete": ([_P], _INT),
     "mdt_cancel": ([_P], _INT),
+    "mdt_stream_progress": ([_P], _INT),
+    "mdt_start_progress_thread": ([_P], _INT),
+    "mdt_stop_progress_thread": ([_P], _INT),
+    "mdt_request_get_status": ([_P, C.POINTER(_INT)], _INT),
     "mdt_batch_create": ([C.POINTER(_P)], _INT),
     "mdt_batch_free": ([C.POINTER(_P)], _INT),
     "mdt_batch_clear": ([_P], _INT),
@@ -455,6 +459,30 @@ class Request:
         f = C.c_int()
         check(_lib.mdt_test(C.byref(self.handle), C.byref(f)), "test")
         return bool(f.value)
+
+    def status(self) -> bool:
+        """mdt_request_get_status: complete as far as progress has seen (no
+        progress, the request is not freed)."""
+        f = C.c_int()
+        check(_lib.mdt_request_get_status(self.handle, C.byref(f)), "request_get_status")
+        return bool(f.value)
+
+
+def _stream_handle(stream):
+    return stream.h if stream is not None else None
+
+
+def stream_progress(stream=None):
+    """mdt_stream_progress (None: general progress)."""
+    check(_lib.mdt_stream_progress(_stream_handle(stream)), "stream_progress")
+
+
+def start_progress_thread(stream=None):
+    check(_lib.mdt_start_progress_thread(_stream_handle(stream)), "start_progress_thread")
+
+
+def stop_progress_thread(stream=None):
+    check(_lib.mdt_stop_progress_thread(_stream_handle(stream)), "stop_progress_thread")
 
 
 def waitall(reqs):

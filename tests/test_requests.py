@@ -26,6 +26,39 @@ def test_c_client_grequests():
         assert "grequest ok" in r.stdout
 
 
+def test_c_client_general_progress():
+    # mdt_stream_progress / progress threads driving generalized requests
+    with tempfile.TemporaryDirectory() as td:
+        exe = os.path.join(td, "progress_check")
+        subprocess.check_call(["gcc", "-std=c11", "-D_POSIX_C_SOURCE=200809L", "-Wall", "-Werror", "-I",
+                               os.path.join(ROOT, "include"), os.path.join(ROOT, "tests", "native", "progress_check.c"),
+                               "-o", exe, LIB, "-lpthread", f"-Wl,-rpath,{os.path.dirname(LIB)}"])
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+        assert r.returncode == 0, r.stdout + r.stderr
+        assert "progress ok" in r.stdout
+
+
+def test_binding_progress_thread_completes_in_background():
+    from paper_2402_12274_amd import mdt
+
+    def poll(g):
+        g.state["polls"] += 1
+        if g.state["polls"] == 50:
+            g.complete()
+
+    g = mdt.GRequest(poll=poll, state={"polls": 0})
+    assert not g.status()
+    mdt.start_progress_thread()
+    try:
+        t0 = time.time()
+        while not g.status() and time.time() - t0 < 30:
+            time.sleep(0.001)
+    finally:
+        mdt.stop_progress_thread()
+    assert g.status() and g.state["polls"] == 50
+    assert g.test() is True  # completed by the thread: freed by this test
+
+
 def test_binding_poll_and_query():
     from paper_2402_12274_amd import mdt
 
@@ -118,3 +151,65 @@ def test_grequest_wraps_stream_work_beside_device_requests():
     mdt.mdt_pack(src.data_ptr(), 1, t, 0, ref.data_ptr(), -1)
     for o in outs:
         assert torch.equal(o, ref)
+
+
+@pytest.mark.gpu
+def test_stream_progress_thread_completes_gpu_requests():
+    """A progress thread on a plain stream records the completion of packs
+    enqueued there (no test or wait in between); a general progress thread
+    completes a generalized request that polls a torch event recorded after
+    work on another stream.  The packed bytes equal the oracle's."""
+    import numpy as np
+    import torch
+
+    from gpu_util import note
+    from oracle import build_type as obuild
+    from paper_2402_12274_amd import inputs, mdt
+
+    note("stream progress thread")
+    dev = torch.device("cuda:0")
+    side = torch.cuda.Stream()
+    ms = mdt.Stream(side.cuda_stream)
+    spec = inputs.halo_face(128, 2, 2, "hi")
+    t = mdt.build_type(spec)
+    host = inputs.random_bytes(128 ** 3 * 8, seed=13)
+    src = torch.from_numpy(host).to(dev)
+    torch.cuda.synchronize()
+    outs = [torch.zeros(t.size(), dtype=torch.uint8, device=dev) for _ in range(4)]
+    mdt.start_progress_thread(ms)
+    try:
+        reqs = [mdt.mdt_pack_enqueue(src.data_ptr(), 1, t, 0, o.data_ptr(), -1, ms, want_request=True)[1]
+                for o in outs]
+        t0 = time.time()
+        while not all(r.status() for r in reqs) and time.time() - t0 < 30:
+            time.sleep(0.0005)
+        assert all(r.status() for r in reqs)
+    finally:
+        mdt.stop_progress_thread(ms)
+    ref = obuild(spec).pack(host, 0, 1)
+    for r, o in zip(reqs, outs):
+        assert r.test() is True
+        assert np.array_equal(o.cpu().numpy(), ref)
+
+    note("general progress thread with a generalized request over a torch event")
+    other = torch.cuda.Stream()
+    out2 = torch.zeros(t.size(), dtype=torch.uint8, device=dev)
+    ms2 = mdt.Stream(other.cuda_stream)
+    mdt.mdt_pack_enqueue(src.data_ptr(), 1, t, 0, out2.data_ptr(), -1, ms2)
+    ev = torch.cuda.Event()
+    ev.record(other)
+
+    def poll(g):
+        if ev.query():
+            g.complete()
+
+    g = mdt.GRequest(poll=poll)
+    mdt.start_progress_thread()
+    try:
+        t0 = time.time()
+        while not g.status() and time.time() - t0 < 30:
+            time.sleep(0.0005)
+    finally:
+        mdt.stop_progress_thread()
+    assert g.status() and g.test() is True
+    assert np.array_equal(out2.cpu().numpy(), ref)
