@@ -735,55 +735,76 @@ static int seg_run(sink *s, int64_t addr, int64_t len)
     return 0;
 }
 
-static void seg_walk(const orc_type *t, seg_sink *S)
+/* The segments of `count` consecutive elements: element r's typemap shifted
+ * by r * extent, in order, through one merging sink, so a run that ends
+ * where the next element's first run starts merges with it. */
+static void seg_walk(const orc_type *t, int64_t count, seg_sink *S)
 {
     S->s.run = seg_run;
     S->s.P = 0;
     S->s.lo = 0;
     S->s.hi = INT64_MAX;
     S->s.skip = 0;
-    emit(t, 0, &S->s);
+    for (int64_t r = 0; r < count && !S->stop; r++) emit(t, r * (t->ub - t->lb), &S->s);
     if (!S->stop && S->have) seg_finalize(S);
 }
 
-int orc_num_segments(const orc_type *t, int64_t *nseg)
+/* count >= 0 and count * size, count * extent representable */
+static int count_ok(const orc_type *t, int64_t count)
+{
+    int64_t x;
+    if (count < 0) return 0;
+    if (count > 0 && __builtin_mul_overflow(count, t->size, &x)) return 0;
+    if (count > 0 && __builtin_mul_overflow(count, t->ub - t->lb, &x)) return 0;
+    return 1;
+}
+
+int orc_num_segments_count(const orc_type *t, int64_t count, int64_t *nseg)
 {
     seg_sink S;
-    if (!t || !nseg) return ORC_ERR_ARG;
+    if (!t || !nseg || !count_ok(t, count)) return ORC_ERR_ARG;
     memset(&S, 0, sizeof S);
     S.mode = 0;
-    seg_walk(t, &S);
+    seg_walk(t, count, &S);
     *nseg = S.nseg;
     return ORC_OK;
 }
 
-int orc_iov_len(const orc_type *t, int64_t max_iov_bytes, int64_t *iov_len, int64_t *actual_bytes)
+int orc_num_segments(const orc_type *t, int64_t *nseg) { return orc_num_segments_count(t, 1, nseg); }
+
+int orc_iov_len_count(const orc_type *t, int64_t count, int64_t max_iov_bytes, int64_t *iov_len,
+                      int64_t *actual_bytes)
 {
     seg_sink S;
-    if (!t || !iov_len || !actual_bytes) return ORC_ERR_ARG;
+    if (!t || !iov_len || !actual_bytes || !count_ok(t, count)) return ORC_ERR_ARG;
     if (max_iov_bytes < -1) return ORC_ERR_ARG;
     memset(&S, 0, sizeof S);
-    if (max_iov_bytes == -1 || max_iov_bytes > t->size) {
+    if (max_iov_bytes == -1 || max_iov_bytes > count * t->size) {
         /* all segments, all bytes */
         S.mode = 0;
-        seg_walk(t, &S);
+        seg_walk(t, count, &S);
         *iov_len = S.nseg;
-        *actual_bytes = t->size;
+        *actual_bytes = count * t->size;
         return ORC_OK;
     }
     S.mode = 1;
     S.max_bytes = max_iov_bytes;
-    seg_walk(t, &S);
+    seg_walk(t, count, &S);
     *iov_len = S.nseg;
     *actual_bytes = S.prefix;
     return ORC_OK;
 }
 
-int orc_iov(const orc_type *t, int64_t iov_offset, int64_t *base, int64_t *len, int64_t max_iov_len,
-            int64_t *actual_iov_len)
+int orc_iov_len(const orc_type *t, int64_t max_iov_bytes, int64_t *iov_len, int64_t *actual_bytes)
+{
+    return orc_iov_len_count(t, 1, max_iov_bytes, iov_len, actual_bytes);
+}
+
+int orc_iov_count(const orc_type *t, int64_t count, int64_t iov_offset, int64_t *base, int64_t *len,
+                  int64_t max_iov_len, int64_t *actual_iov_len)
 {
     seg_sink S;
-    if (!t || !actual_iov_len || iov_offset < 0 || max_iov_len < 0) return ORC_ERR_ARG;
+    if (!t || !actual_iov_len || iov_offset < 0 || max_iov_len < 0 || !count_ok(t, count)) return ORC_ERR_ARG;
     if (max_iov_len > 0 && (!base || !len)) return ORC_ERR_ARG;
     memset(&S, 0, sizeof S);
     S.mode = 2;
@@ -791,9 +812,15 @@ int orc_iov(const orc_type *t, int64_t iov_offset, int64_t *base, int64_t *len, 
     S.m = max_iov_len;
     S.obase = base;
     S.olen = len;
-    if (max_iov_len > 0) seg_walk(t, &S);
+    if (max_iov_len > 0) seg_walk(t, count, &S);
     *actual_iov_len = S.got;
     return ORC_OK;
+}
+
+int orc_iov(const orc_type *t, int64_t iov_offset, int64_t *base, int64_t *len, int64_t max_iov_len,
+            int64_t *actual_iov_len)
+{
+    return orc_iov_count(t, 1, iov_offset, base, len, max_iov_len, actual_iov_len);
 }
 
 /* ------------------------------------------------------------------ */

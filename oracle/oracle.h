@@ -73,6 +73,14 @@ int orc_num_segments(const orc_type *t, int64_t *nseg);
 int orc_iov_len(const orc_type *t, int64_t max_iov_bytes, int64_t *iov_len, int64_t *actual_bytes);
 int orc_iov(const orc_type *t, int64_t iov_offset, int64_t *base, int64_t *len, int64_t max_iov_len,
             int64_t *actual_iov_len);
+/* The same queries over `count` consecutive elements (element r at r *
+ * extent); a segment may then span an element boundary.  count = 1 is the
+ * single-type form above; count = 0 has no segments. */
+int orc_num_segments_count(const orc_type *t, int64_t count, int64_t *nseg);
+int orc_iov_len_count(const orc_type *t, int64_t count, int64_t max_iov_bytes, int64_t *iov_len,
+                      int64_t *actual_bytes);
+int orc_iov_count(const orc_type *t, int64_t count, int64_t iov_offset, int64_t *base, int64_t *len,
+                  int64_t max_iov_len, int64_t *actual_iov_len);
 
 /* Pack bytes [inoffset, inoffset + actual) of the packed stream of
  * (count x t) read from `origin` into `out`; actual = clamp(count*size -

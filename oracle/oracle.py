@@ -87,6 +87,9 @@ def load():
         "orc_num_segments": ([_P, _I64P], C.c_int),
         "orc_iov_len": ([_P, _I64, _I64P, _I64P], C.c_int),
         "orc_iov": ([_P, _I64, _I64P, _I64P, _I64, _I64P], C.c_int),
+        "orc_num_segments_count": ([_P, _I64, _I64P], C.c_int),
+        "orc_iov_len_count": ([_P, _I64, _I64, _I64P, _I64P], C.c_int),
+        "orc_iov_count": ([_P, _I64, _I64, _I64P, _I64P, _I64, _I64P], C.c_int),
         "orc_pack": ([_P, _I64, _P, _I64, _P, _I64, _I64P], C.c_int),
         "orc_pack_mt": ([_P, _I64, _P, _I64, _P, _I64, _I64P, C.c_int], C.c_int),
         "orc_unpack": ([_P, _I64, _P, _I64, _P, _I64, _I64P], C.c_int),
@@ -124,24 +127,24 @@ class OType:
         return dict(size=size, lb=lb, ub=ub, extent=ub - lb, true_lb=tlb, true_ub=tub,
                     true_extent=tub - tlb, align=align, explicit=bool(expl), entries=nent)
 
-    # -- segment queries ----------------------------------------------
-    def num_segments(self) -> int:
+    # -- segment queries (count consecutive elements; 1 = the type alone) --
+    def num_segments(self, count: int = 1) -> int:
         n = C.c_int64()
-        _check(load().orc_num_segments(self.ptr, C.byref(n)))
+        _check(load().orc_num_segments_count(self.ptr, count, C.byref(n)))
         return n.value
 
-    def iov_len(self, max_iov_bytes: int):
+    def iov_len(self, max_iov_bytes: int, count: int = 1):
         a, b = C.c_int64(), C.c_int64()
-        _check(load().orc_iov_len(self.ptr, max_iov_bytes, C.byref(a), C.byref(b)))
+        _check(load().orc_iov_len_count(self.ptr, count, max_iov_bytes, C.byref(a), C.byref(b)))
         return a.value, b.value
 
-    def iov(self, iov_offset: int, max_iov_len: int):
+    def iov(self, iov_offset: int, max_iov_len: int, count: int = 1):
         m = max(0, max_iov_len)
         base = np.zeros(max(m, 1), np.int64)
         ln = np.zeros(max(m, 1), np.int64)
         got = C.c_int64()
-        _check(load().orc_iov(self.ptr, iov_offset, base.ctypes.data_as(_I64P), ln.ctypes.data_as(_I64P),
-                              max_iov_len, C.byref(got)))
+        _check(load().orc_iov_count(self.ptr, count, iov_offset, base.ctypes.data_as(_I64P),
+                                    ln.ctypes.data_as(_I64P), max_iov_len, C.byref(got)))
         return base[: got.value].copy(), ln[: got.value].copy()
 
     # -- pack / unpack --------------------------------------------------

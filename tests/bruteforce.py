@@ -136,6 +136,13 @@ def typemap(spec) -> TM:
     raise ValueError(k)
 
 
+def repeat(tm: TM, count: int) -> TM:
+    """The typemap of `count` consecutive elements (element r shifted by
+    r * extent), as one entry list."""
+    entries = [(r * tm.extent + d, s) for r in range(count) for d, s in tm.entries]
+    return TM(entries, tm.lb, tm.lb + count * tm.extent, tm.align, tm.explicit)
+
+
 def segments(tm: TM):
     """Maximal runs, in map order, of entries that start where the previous ended."""
     segs = []

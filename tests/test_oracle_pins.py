@@ -237,6 +237,61 @@ def test_oracle_vs_bruteforce(i):
                 assert np.array_equal(dst2, exp2)
 
 
+@pytest.mark.parametrize("i", range(0, len(SPECS), 2))
+def test_oracle_iov_count_vs_bruteforce(i):
+    # segment queries over count consecutive elements: the brute-force list
+    # of count shifted copies, merged where one element's last run touches
+    # the next element's first
+    spec = SPECS[i]
+    tm = bf.typemap(spec)
+    t = build_type(spec)
+    for count in (0, 2, 3):
+        rt = bf.repeat(tm, count)
+        segs = bf.segments(rt)
+        assert t.num_segments(count) == len(segs), (spec, count)
+        b, ln = t.iov(0, len(segs) + 3, count)
+        assert list(zip(b.tolist(), ln.tolist())) == segs, (spec, count)
+        for off in range(0, len(segs) + 2, max(1, len(segs) // 7)):
+            for m in (0, 1, 3):
+                b, ln = t.iov(off, m, count)
+                assert list(zip(b.tolist(), ln.tolist())) == bf.iov(rt, off, m), (spec, count, off, m)
+        for mb in [-1] + list(range(0, rt.size + 2)):
+            assert t.iov_len(mb, count) == bf.iov_len(rt, mb), (spec, count, mb)
+
+
+def test_iov_count_closed_forms():
+    # worked by hand: resized(vector(2, 1, 2, INT32), lb 0, extent 12) puts
+    # element r's runs at 12r and 12r + 8 (4 bytes each): the second run of
+    # one element ends where the next element's first begins, so k elements
+    # give 1 + k segments: 4 bytes, k - 1 merged 8-byte runs, 4 bytes
+    spec = ("resized", 0, 12, ("vector", 2, 1, 2, ("basic", "INT32")))
+    t = build_type(spec)
+    for k in (1, 2, 3, 7):
+        assert t.num_segments(k) == 1 + k
+        b, ln = t.iov(0, 100, k)
+        exp = [(0, 4)] + [(12 * r + 8, 8) for r in range(k - 1)] + [(12 * (k - 1) + 8, 4)]
+        assert list(zip(b.tolist(), ln.tolist())) == exp
+        # byte budgets: whole segments only (the merged run spans bytes 4..12)
+        assert t.iov_len(11, k) == ((1, 4) if k > 1 else (2, 8))
+        if k > 2:
+            assert t.iov_len(12, k) == (2, 12) and t.iov_len(19, k) == (2, 12) and t.iov_len(20, k) == (3, 20)
+    # a contiguous type: all elements form one segment
+    c = build_type(("contiguous", 3, ("basic", "DOUBLE")))
+    assert t.num_segments(0) == 0 and c.num_segments(5) == 1
+    assert [x.tolist() for x in c.iov(0, 4, 5)] == [[0], [120]]
+    assert c.iov_len(119, 5) == (0, 0) and c.iov_len(120, 5) == (1, 120) and c.iov_len(-1, 5) == (1, 120)
+    # the C1 vector: vector(1024, 1, 2, DOUBLE) has extent 16,376 and its
+    # last run [16368, 16376) ends where the next element's first run
+    # begins, so k elements give 1024k - (k - 1) segments, the merged ones
+    # 16 bytes long
+    v = build_type(("vector", 1024, 1, 2, ("basic", "DOUBLE")))
+    assert v.num_segments(3) == 3070
+    b, ln = v.iov(1022, 3, 3)
+    assert b.tolist() == [16352, 16368, 16392] and ln.tolist() == [8, 16, 8]
+    with pytest.raises(OracleError):
+        v.iov_len(-1, -1)
+
+
 # ---------------------------------------------------------------------------
 # invariants and error rules
 
