@@ -275,6 +275,21 @@ MDT_API int mdt_type_iov_len(mdt_type t, mdt_count max_iov_bytes, mdt_count *iov
 MDT_API int mdt_type_iov(mdt_type t, mdt_count iov_offset, mdt_iov *iov, mdt_count max_iov_len,
                          mdt_count *actual_iov_len);
 
+/* The same two queries over count consecutive elements (Derived Datatypes,
+ * Extension: the queries are stated for one datatype; this is the form for
+ * a buffer of count elements, element r at r * extent).  Segments are those
+ * of the count-fold typemap, merged where they touch, so an element's last
+ * segment merges with the next element's first when it ends where that one
+ * starts (the layout of contiguous(count, t)).  count = 1 is
+ * mdt_type_iov_len / mdt_type_iov; count = 0 has no segments.  max_iov_bytes
+ * is compared with count * size.  Errors: MDT_ERR_ARG for count < 0,
+ * MDT_ERR_COUNT when count * size, count * extent or the segment count
+ * overflows. */
+MDT_API int mdt_type_iov_len_count(mdt_type t, mdt_count count, mdt_count max_iov_bytes, mdt_count *iov_len,
+                                   mdt_count *actual_iov_bytes);
+MDT_API int mdt_type_iov_count(mdt_type t, mdt_count count, mdt_count iov_offset, mdt_iov *iov,
+                               mdt_count max_iov_len, mdt_count *actual_iov_len);
+
 /* Blocking pack of bytes [inoffset, inoffset + actual) of the packed stream
  * of (incount x t) read from device buffer inbuf (the origin) into device
  * buffer outbuf; actual = clamp(incount*size - inoffset, 0, max_pack_bytes),
@@ -331,6 +346,10 @@ MDT_API int mdt_typed_copy_enqueue(const void *src, mdt_count srccount, mdt_type
  * on s.  *actual_iov_len is returned immediately. */
 MDT_API int mdt_type_iov_enqueue(mdt_type t, mdt_count iov_offset, mdt_iov *dev_iov, mdt_count max_iov_len,
                                  const void *base, mdt_count *actual_iov_len, mdt_stream s, mdt_request *req);
+/* Device flatten of the count form (mdt_type_iov_count's segments). */
+MDT_API int mdt_type_iov_count_enqueue(mdt_type t, mdt_count count, mdt_count iov_offset, mdt_iov *dev_iov,
+                                       mdt_count max_iov_len, const void *base, mdt_count *actual_iov_len,
+                                       mdt_stream s, mdt_request *req);
 /* Complete a request (from an enqueue or batch launch, or a generalized
  * request): mdt_wait blocks; mdt_test sets *flag = 1 and frees the request
  * if it has completed, else *flag = 0.  Completed requests are freed and

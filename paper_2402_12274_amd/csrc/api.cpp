@@ -338,4 +338,27 @@ MDT_API int mdt_type_iov_enqueue(mdt_type t, mdt_count iov_offset, mdt_iov *dev_
     return MDT_SUCCESS;
 }
 
+MDT_API int mdt_type_iov_count_enqueue(mdt_type t, mdt_count count, mdt_count iov_offset, mdt_iov *dev_iov,
+                                       mdt_count max_iov_len, const void *base, mdt_count *actual_iov_len,
+                                       mdt_stream s, mdt_request *req)
+{
+    if (!valid_stream(s) || !actual_iov_len || count < 0 || iov_offset < 0 || max_iov_len < 0) return MDT_ERR_ARG;
+    if (max_iov_len > 0 && !dev_iov) return MDT_ERR_ARG;
+    Compiled *C;
+    DeviceTables *D;
+    int64_t total;
+    int rc = prepare(t, 1, &C, &D, &total);
+    if (rc) return rc;
+    SegCount sc{};
+    rc = element_segments(reinterpret_cast<TypeNode *>(t), &sc, count);
+    if (rc) return rc;
+    int64_t m = iov_offset >= sc.total ? 0 : std::min<int64_t>(max_iov_len, sc.total - iov_offset);
+    rc = launch_flatten(C, D, iov_offset, m, dev_iov, base, s->s, &sc);
+    if (rc) return rc;
+    rc = request_from_stream(s->s, req, s);
+    if (rc) return rc;
+    *actual_iov_len = m;
+    return MDT_SUCCESS;
+}
+
 }  // extern "C"

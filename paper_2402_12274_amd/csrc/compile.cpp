@@ -1045,6 +1045,147 @@ int host_iov(TypeNode *t, int64_t off, mdt_iov *iov, int64_t m, int64_t *actual)
     return MDT_SUCCESS;
 }
 
+// ---- segments of count consecutive elements --------------------------
+//
+// Element r is the element's typemap shifted by r * extent, so the count
+// form's segments are the element's segments repeated, except where the
+// element's last segment ends exactly where the next element's first one
+// starts (first_addr + extent == last_end): those two merge across the
+// boundary.  With n element segments that gives 1 + count*(n-1) segments
+// (one in all when n = 1), in the order seg 0 of element 0, then for each
+// element q its segments 1..n-2 followed by the bridge (its last segment
+// merged with element q+1's first; element count-1's last stands alone).
+
+int element_segments(TypeNode *t, SegCount *sc, int64_t count)
+{
+    int rc = commit_type(t);
+    if (rc) return rc;
+    Compiled *C = t->comp.get();
+    if (!C->merge_free) {
+        rc = build_segment_table(C);
+        if (rc) return rc;
+    }
+    if (count < 0) return MDT_ERR_ARG;
+    int64_t x;
+    if (__builtin_mul_overflow(count, t->size, &x) || __builtin_mul_overflow(count, t->extent(), &x))
+        return MDT_ERR_COUNT;
+    sc->C = C;
+    sc->count = count;
+    sc->extent = t->extent();
+    sc->size = t->size;
+    sc->n = C->merge_free ? C->nruns : (int64_t)C->seg_addr.size();
+    sc->merge = false;
+    if (sc->n > 0 && count > 1) {
+        int64_t a0, l0, al, ll;
+        seg_of(*sc, 0, &a0, &l0);
+        seg_of(*sc, sc->n - 1, &al, &ll);
+        sc->merge = a0 + sc->extent == al + ll;
+    }
+    if (count == 0 || sc->n == 0) sc->total = 0;
+    else if (!sc->merge) {
+        if (__builtin_mul_overflow(count, sc->n, &sc->total)) return MDT_ERR_COUNT;
+    } else sc->total = sc->n == 1 ? 1 : 1 + count * (sc->n - 1);
+    return MDT_SUCCESS;
+}
+
+// segment j (< n) of one element
+void seg_of(const SegCount &sc, int64_t j, int64_t *addr, int64_t *len)
+{
+    if (sc.C->merge_free) {
+        RunInfo r = run_at(sc.C->host, (uint64_t)j);
+        *addr = r.addr;
+        *len = r.len;
+    } else {
+        *addr = sc.C->seg_addr[(size_t)j];
+        *len = sc.C->seg_len[(size_t)j];
+    }
+}
+
+// segment g (< total) of the count form
+void seg_count_at(const SegCount &sc, int64_t g, int64_t *addr, int64_t *len)
+{
+    if (!sc.merge) {
+        const int64_t q = g / sc.n, j = g % sc.n;
+        seg_of(sc, j, addr, len);
+        *addr += q * sc.extent;
+        return;
+    }
+    if (sc.n == 1) {
+        seg_of(sc, 0, addr, len);
+        *len *= sc.count;
+        return;
+    }
+    if (g == 0) {
+        seg_of(sc, 0, addr, len);
+        return;
+    }
+    const int64_t q = (g - 1) / (sc.n - 1), j = (g - 1) % (sc.n - 1) + 1;
+    seg_of(sc, j, addr, len);
+    *addr += q * sc.extent;
+    if (j == sc.n - 1 && q < sc.count - 1) {
+        int64_t a0, l0;
+        seg_of(sc, 0, &a0, &l0);
+        *len += l0;
+    }
+}
+
+int host_iov_len_count(TypeNode *t, int64_t count, int64_t max_bytes, int64_t *n, int64_t *bytes)
+{
+    SegCount sc{};
+    int rc = element_segments(t, &sc, count);
+    if (rc) return rc;
+    const int64_t all = count * t->size;
+    if (max_bytes == -1 || max_bytes >= all) {
+        *n = sc.total;
+        *bytes = all;
+        return MDT_SUCCESS;
+    }
+    // max_bytes < all, so the element size is positive: byte max_bytes lies
+    // in element r at rem, inside element segment j (P_j <= rem < P_{j+1})
+    int64_t r = max_bytes / t->size, rem = max_bytes - r * t->size, j, pj;
+    if (sc.C->merge_free) {
+        run_of_byte(*sc.C, rem, &j, &pj);
+    } else {
+        auto it = std::upper_bound(sc.C->seg_pre.begin(), sc.C->seg_pre.end(), rem);
+        j = (int64_t)(it - sc.C->seg_pre.begin()) - 1;
+        pj = sc.C->seg_pre[(size_t)j];
+    }
+    if (!sc.merge) {
+        *n = r * sc.n + j;
+        *bytes = r * t->size + pj;
+        return MDT_SUCCESS;
+    }
+    if (sc.n == 1 || (r == 0 && j == 0)) {  // inside the first segment
+        *n = 0;
+        *bytes = 0;
+        return MDT_SUCCESS;
+    }
+    if (j == 0) {  // element r's first bytes belong to the bridge from element r-1
+        r -= 1;
+        j = sc.n - 1;
+        pj = t->size - (sc.C->merge_free ? run_at(sc.C->host, (uint64_t)j).len : sc.C->seg_len[(size_t)j]);
+    }
+    *n = 1 + r * (sc.n - 1) + (j - 1);
+    *bytes = r * t->size + pj;
+    return MDT_SUCCESS;
+}
+
+int host_iov_count(TypeNode *t, int64_t count, int64_t off, mdt_iov *iov, int64_t m, int64_t *actual)
+{
+    SegCount sc{};
+    int rc = element_segments(t, &sc, count);
+    if (rc) return rc;
+    const int64_t end = off >= sc.total ? off : std::min(sc.total, off + m);
+    for (int64_t g = off; g < end; g++) {
+        int64_t a, l;
+        seg_count_at(sc, g, &a, &l);
+        iov[g - off].iov_base = (void *)(intptr_t)a;
+        iov[g - off].iov_len = l;
+    }
+    *actual = end - off;
+    return MDT_SUCCESS;
+}
+
 int check_unpack_overlap(Compiled *c, int64_t count)
 {
     std::lock_guard<std::mutex> g(c->ov_mu);

@@ -144,6 +144,19 @@ int commit_type(TypeNode *t);
 int host_iov_len(TypeNode *t, int64_t max_bytes, int64_t *n, int64_t *bytes);
 int host_iov(TypeNode *t, int64_t off, mdt_iov *iov, int64_t m, int64_t *actual);
 int check_unpack_overlap(Compiled *c, int64_t count);  // MDT_SUCCESS or MDT_ERR_OVERLAP / NO_MEM
+// segments of count consecutive elements (compile.cpp)
+struct SegCount {
+    Compiled *C;
+    int64_t count, extent, size;
+    int64_t n;      // segments of one element
+    bool merge;     // an element's last segment merges with the next element's first
+    int64_t total;  // segments of the count form
+};
+int element_segments(TypeNode *t, SegCount *sc, int64_t count);
+void seg_of(const SegCount &sc, int64_t j, int64_t *addr, int64_t *len);
+void seg_count_at(const SegCount &sc, int64_t g, int64_t *addr, int64_t *len);
+int host_iov_len_count(TypeNode *t, int64_t count, int64_t max_bytes, int64_t *n, int64_t *bytes);
+int host_iov_count(TypeNode *t, int64_t count, int64_t off, mdt_iov *iov, int64_t m, int64_t *actual);
 int build_segment_table(Compiled *c);
 
 // device.hip

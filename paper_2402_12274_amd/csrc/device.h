@@ -43,8 +43,9 @@ struct CopyArgs {
 XferArgs make_args(const void *typed, void *packed, int64_t off, int64_t nbytes);
 int launch_copy(const DevLayout &Ls, const DevLayout &Ld, const CopyArgs &A, hipStream_t s);
 int launch_xfer(const DevLayout &L, const XferArgs &A, bool unpack, hipStream_t s);
+// sc: the count form's segments (NULL or count 1: one element)
 int launch_flatten(Compiled *c, DeviceTables *d, int64_t off, int64_t m, mdt_iov *out, const void *base,
-                   hipStream_t s);
+                   hipStream_t s, const SegCount *sc = nullptr);
 int64_t default_tile_chunks(int64_t nchunks);
 // the dense record path applies to this request
 bool use_dense(const DevLayout &L, const XferArgs &A, bool unpack);

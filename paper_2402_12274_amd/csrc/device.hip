@@ -234,6 +234,54 @@ __global__ __launch_bounds__(256) void flatten_table_kernel(const mdt_iov *segs,
     out[i].iov_len = s.iov_len;
 }
 
+// flatten over count consecutive elements: lane i writes segment off + i of
+// the count form (the element's segments repeated at multiples of the
+// extent; with `merge`, each element's last segment joined to the next
+// element's first).  TABLE: segments come from the merged-segment table,
+// else from the layout's runs.
+template <bool TABLE>
+__global__ __launch_bounds__(256) void flatten_count_kernel(const DevLayout L, const mdt_iov *segs, int64_t n,
+                                                            int merge, int64_t count, int64_t extent, int64_t off,
+                                                            int64_t m, mdt_iov *out, uintptr_t base)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    const int64_t g = off + i;
+    auto seg = [&](int64_t j, int64_t *a, int64_t *l) {
+        if (TABLE) {
+            mdt_iov v = segs[j];
+            *a = (int64_t)(intptr_t)v.iov_base;
+            *l = v.iov_len;
+        } else {
+            RunInfo r = run_at(L, (uint64_t)j);
+            *a = r.addr;
+            *l = r.len;
+        }
+    };
+    int64_t a, l;
+    if (!merge) {
+        const int64_t q = g / n;
+        seg(g - q * n, &a, &l);
+        a += q * extent;
+    } else if (n == 1) {
+        seg(0, &a, &l);
+        l *= count;
+    } else if (g == 0) {
+        seg(0, &a, &l);
+    } else {
+        const int64_t q = (g - 1) / (n - 1), j = (g - 1) - q * (n - 1) + 1;
+        seg(j, &a, &l);
+        a += q * extent;
+        if (j == n - 1 && q < count - 1) {
+            int64_t a0, l0;
+            seg(0, &a0, &l0);
+            l += l0;
+        }
+    }
+    out[i].iov_base = (void *)(base + (uintptr_t)a);
+    out[i].iov_len = l;
+}
+
 // ---------------------------------------------------------------------------
 // launch
 
@@ -371,12 +419,18 @@ XferArgs make_args(const void *typed, void *packed, int64_t off, int64_t nbytes)
 }
 
 int launch_flatten(Compiled *c, DeviceTables *d, int64_t off, int64_t m, mdt_iov *out, const void *base,
-                   hipStream_t s)
+                   hipStream_t s, const SegCount *sc)
 {
     if (m <= 0) return MDT_SUCCESS;
+    if ((m + 255) / 256 > (int64_t)UINT32_MAX) return MDT_ERR_COUNT;
     dim3 g((unsigned)((m + 255) / 256)), b(256);
+    const bool counted = sc && sc->count != 1;
     if (c->merge_free) {
-        hipLaunchKernelGGL(flatten_kernel, g, b, 0, s, d->lay, off, m, out, (uintptr_t)base);
+        if (counted)
+            hipLaunchKernelGGL(flatten_count_kernel<false>, g, b, 0, s, d->lay, (const mdt_iov *)nullptr, sc->n,
+                               (int)sc->merge, sc->count, sc->extent, off, m, out, (uintptr_t)base);
+        else
+            hipLaunchKernelGGL(flatten_kernel, g, b, 0, s, d->lay, off, m, out, (uintptr_t)base);
     } else {
         std::lock_guard<std::mutex> lk(c->dev_mu);
         if (!d->d_segs) {
@@ -392,7 +446,11 @@ int launch_flatten(Compiled *c, DeviceTables *d, int64_t off, int64_t m, mdt_iov
             HIPCHK(hipMemcpy(p, h.data(), n * sizeof(mdt_iov), hipMemcpyHostToDevice));
             d->d_segs = (mdt_iov *)p;
         }
-        hipLaunchKernelGGL(flatten_table_kernel, g, b, 0, s, d->d_segs, off, m, out, (uintptr_t)base);
+        if (counted)
+            hipLaunchKernelGGL(flatten_count_kernel<true>, g, b, 0, s, d->lay, (const mdt_iov *)d->d_segs, sc->n,
+                               (int)sc->merge, sc->count, sc->extent, off, m, out, (uintptr_t)base);
+        else
+            hipLaunchKernelGGL(flatten_table_kernel, g, b, 0, s, d->d_segs, off, m, out, (uintptr_t)base);
     }
     HIPCHK(hipGetLastError());
     return MDT_SUCCESS;

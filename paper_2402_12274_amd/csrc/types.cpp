@@ -736,6 +736,27 @@ MDT_API int mdt_type_iov(mdt_type t, mdt_count iov_offset, mdt_iov *iov, mdt_cou
     return host_iov(n, iov_offset, iov, max_iov_len, actual_iov_len);
 }
 
+MDT_API int mdt_type_iov_len_count(mdt_type t, mdt_count count, mdt_count max_iov_bytes, mdt_count *iov_len,
+                                   mdt_count *actual_iov_bytes)
+{
+    CHECK_TYPE(t);
+    if (!iov_len || !actual_iov_bytes || max_iov_bytes < -1 || count < 0) return MDT_ERR_ARG;
+    TypeNode *n = as_node(t);
+    if (!n->committed.load() && !n->predefined) return MDT_ERR_TYPE;
+    return host_iov_len_count(n, count, max_iov_bytes, iov_len, actual_iov_bytes);
+}
+
+MDT_API int mdt_type_iov_count(mdt_type t, mdt_count count, mdt_count iov_offset, mdt_iov *iov,
+                               mdt_count max_iov_len, mdt_count *actual_iov_len)
+{
+    CHECK_TYPE(t);
+    if (!actual_iov_len || count < 0 || iov_offset < 0 || max_iov_len < 0 || (max_iov_len > 0 && !iov))
+        return MDT_ERR_ARG;
+    TypeNode *n = as_node(t);
+    if (!n->committed.load() && !n->predefined) return MDT_ERR_TYPE;
+    return host_iov_count(n, count, iov_offset, iov, max_iov_len, actual_iov_len);
+}
+
 MDT_API const char *mdt_error_string(int code)
 {
     switch (code) {

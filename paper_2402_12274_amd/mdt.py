@@ -109,6 +109,8 @@ _SIGS = {
     "mdt_type_get_true_extent": ([_P, _I64P, _I64P], _INT),
     "mdt_type_iov_len": ([_P, _I64, _I64P, _I64P], _INT),
     "mdt_type_iov": ([_P, _I64, C.POINTER(Iov), _I64, _I64P], _INT),
+    "mdt_type_iov_len_count": ([_P, _I64, _I64, _I64P, _I64P], _INT),
+    "mdt_type_iov_count": ([_P, _I64, _I64, C.POINTER(Iov), _I64, _I64P], _INT),
     "mdt_pack": ([_P, _I64, _P, _I64, _P, _I64, _I64P], _INT),
     "mdt_unpack": ([_P, _I64, _P, _I64, _P, _I64, _I64P], _INT),
     "mdt_typed_copy": ([_P, _I64, _P, _P, _I64, _P, _I64, _I64, _I64P], _INT),
@@ -118,6 +120,7 @@ _SIGS = {
     "mdt_pack_enqueue": ([_P, _I64, _P, _I64, _P, _I64, _I64P, _P, C.POINTER(_P)], _INT),
     "mdt_unpack_enqueue": ([_P, _I64, _P, _I64, _P, _I64, _I64P, _P, C.POINTER(_P)], _INT),
     "mdt_type_iov_enqueue": ([_P, _I64, _P, _I64, _P, _I64P, _P, C.POINTER(_P)], _INT),
+    "mdt_type_iov_count_enqueue": ([_P, _I64, _I64, _P, _I64, _P, _I64P, _P, C.POINTER(_P)], _INT),
     "mdt_wait": ([C.POINTER(_P)], _INT),
     "mdt_test": ([C.POINTER(_P), C.POINTER(_INT)], _INT),
     "mdt_waitall": ([_INT, C.POINTER(_P)], _INT),
@@ -240,16 +243,24 @@ class Type:
         check(_lib.mdt_type_get_true_extent(self.h, C.byref(a), C.byref(b)), "true_extent")
         return a.value, b.value
 
-    def iov_len(self, max_iov_bytes: int):
+    def iov_len(self, max_iov_bytes: int, count: int = None):
+        """mdt_type_iov_len, or mdt_type_iov_len_count when count is given."""
         a, b = C.c_int64(), C.c_int64()
-        check(_lib.mdt_type_iov_len(self.h, max_iov_bytes, C.byref(a), C.byref(b)), "iov_len")
+        if count is None:
+            check(_lib.mdt_type_iov_len(self.h, max_iov_bytes, C.byref(a), C.byref(b)), "iov_len")
+        else:
+            check(_lib.mdt_type_iov_len_count(self.h, count, max_iov_bytes, C.byref(a), C.byref(b)), "iov_len_count")
         return a.value, b.value
 
-    def iov(self, iov_offset: int, max_iov_len: int):
+    def iov(self, iov_offset: int, max_iov_len: int, count: int = None):
+        """mdt_type_iov, or mdt_type_iov_count when count is given."""
         m = max(0, max_iov_len)
         buf = (Iov * max(1, m))()
         got = C.c_int64()
-        check(_lib.mdt_type_iov(self.h, iov_offset, buf, max_iov_len, C.byref(got)), "iov")
+        if count is None:
+            check(_lib.mdt_type_iov(self.h, iov_offset, buf, max_iov_len, C.byref(got)), "iov")
+        else:
+            check(_lib.mdt_type_iov_count(self.h, count, iov_offset, buf, max_iov_len, C.byref(got)), "iov_count")
         n = got.value
         base = np.array([(buf[i].iov_base or 0) for i in range(n)], dtype=np.uint64).view(np.int64)
         ln = np.array([buf[i].iov_len for i in range(n)], dtype=np.int64)
@@ -594,6 +605,16 @@ def mdt_type_iov_enqueue(t: Type, iov_offset: int, dev_iov: int, max_iov_len: in
     req = Request() if want_request else None
     check(_lib.mdt_type_iov_enqueue(t.h, iov_offset, _P(dev_iov), max_iov_len, _P(base), C.byref(n), stream.h,
                                     C.byref(req.handle) if req else None), "mdt_type_iov_enqueue")
+    return n.value, req
+
+
+def mdt_type_iov_count_enqueue(t: Type, count: int, iov_offset: int, dev_iov: int, max_iov_len: int, base: int,
+                               stream: Stream, want_request: bool = False):
+    n = C.c_int64()
+    req = Request() if want_request else None
+    check(_lib.mdt_type_iov_count_enqueue(t.h, count, iov_offset, _P(dev_iov), max_iov_len, _P(base), C.byref(n),
+                                          stream.h, C.byref(req.handle) if req else None),
+          "mdt_type_iov_count_enqueue")
     return n.value, req
 
 

@@ -283,6 +283,35 @@ def test_device_flatten_matches_oracle(mdt):
     assert ctypes.sizeof(mdt.Iov) == 16
 
 
+def test_device_flatten_count_matches_oracle(mdt):
+    # the count form on the device: element segments repeated at multiples
+    # of the extent, merged across element boundaries where they touch
+    torch = pytest.importorskip("torch")
+    specs = [inputs.vector_small(), inputs.particle_struct(), inputs.halo_face(64, 1, 2, "lo"),
+             ("resized", 0, 12, ("vector", 2, 1, 2, ("basic", "INT32"))), ("resized", 0, 24, ("contiguous", 3, inputs.DOUBLE)),
+             ("contiguous", 4, ("vector", 3, 1, 2, inputs.DOUBLE))]
+    lens, disps = inputs.hindexed_blocks(nblocks=3000, span=1 << 20, seed=12)
+    specs.append(inputs.hindexed_type(lens, disps))
+    specs += tiny_specs(6, 20)
+    s = mdt.Stream(0)
+    for spec in specs:
+        t = mdt.build_type(spec)
+        o = obuild(spec)
+        for count in (0, 2, 5):
+            note(f"flatten count={count} {str(spec)[:70]}")
+            nseg = o.iov_len(-1, count)[0]
+            for off, m in [(0, nseg), (nseg // 3, 777), (max(nseg - 2, 0), 5), (nseg, 5)]:
+                want = max(0, min(m, nseg - off))
+                out = torch.zeros(max(1, want) * 2, dtype=torch.int64, device="cuda")
+                base = 1 << 40
+                got, _ = mdt.mdt_type_iov_count_enqueue(t, count, off, out.data_ptr(), m, base, s)
+                torch.cuda.synchronize()
+                ob, ol = o.iov(off, m, count)
+                assert got == ob.size == want
+                h = out.cpu().numpy()[: 2 * got].reshape(-1, 2)
+                assert np.array_equal(h[:, 0] - base, ob) and np.array_equal(h[:, 1], ol), (spec, count, off)
+
+
 def test_darray_random_small(mdt):
     """Random distributed arrays (every distribution, both orders, gapped
     element types): full and partial packs at odd output alignments and

@@ -260,3 +260,58 @@ def test_darray_cyclic_is_constant_size():
     t = mdt.build_type(("darray", 2, 1, [10], ["cyclic"], [3], [2], "C", ("basic", "INT32")))
     b, ln = t.iov(0, 4)
     assert list(b) == [12, 36] and list(ln) == [12, 4]
+
+
+def _cmp_segments_count(t, o, count, probe_all=True):
+    nseg, size = o.iov_len(-1, count)
+    assert t.iov_len(-1, count) == (nseg, size)
+    ob, ol = o.iov(0, nseg, count)
+    tb, tl = t.iov(0, nseg + 2, count)
+    assert np.array_equal(tb, ob) and np.array_equal(tl, ol), count
+    budgets = range(0, size + 2) if probe_all else \
+        [int(x) for x in np.random.Generator(np.random.PCG64(nseg)).integers(0, size + 1, 200)] + [0, size - 1, size]
+    for mb in budgets:
+        assert t.iov_len(mb, count) == o.iov_len(mb, count), (count, mb)
+    for off in (0, 1, nseg // 2, max(nseg - 1, 0), nseg, nseg + 3):
+        for m in (0, 1, 3, 17):
+            b1, l1 = t.iov(off, m, count)
+            b2, l2 = o.iov(off, m, count)
+            assert np.array_equal(b1, b2) and np.array_equal(l1, l2), (count, off, m)
+
+
+@pytest.mark.parametrize("i", range(0, len(SPECS), 3))
+def test_iov_count_matches_oracle(i):
+    # the count form of the segment queries, on random types (merge-free
+    # layouts and those with a merged-segment table) and counts 0..4
+    spec = SPECS[i]
+    t = mdt.build_type(spec)
+    o = obuild(spec)
+    for count in (0, 1, 2, 4):
+        _cmp_segments_count(t, o, count)
+
+
+def test_iov_count_boundary_merges_and_errors():
+    D = inputs.DOUBLE
+    cases = [("resized", 0, 12, ("vector", 2, 1, 2, ("basic", "INT32"))),   # last run touches the next element
+             inputs.vector_small(),                                          # ditto (extent = last run's end)
+             ("contiguous", 3, D),                                           # one segment for every count
+             ("resized", 0, 24, ("contiguous", 3, D)),                       # elements touch: one segment
+             ("resized", 0, 32, ("contiguous", 3, D)),                       # a gap between elements
+             ("resized", -8, 16, ("hindexed", [1, 1], [8, -8], D)),          # map order descending
+             inputs.particle_struct()]
+    for spec in cases:
+        t = mdt.build_type(spec)
+        o = obuild(spec)
+        for count in (0, 1, 2, 3, 17):
+            _cmp_segments_count(t, o, count)
+    t = mdt.build_type(inputs.vector_small())
+    with pytest.raises(mdt.MdtError) as e:
+        t.iov_len(-1, -1)
+    assert e.value.code == mdt.ERR_ARG
+    with pytest.raises(mdt.MdtError) as e:
+        t.iov(0, 1, 1 << 62)
+    assert e.value.code == mdt.ERR_COUNT
+    # the worked example's halo face over a count: the library's counted
+    # segments at full size (sampled budgets)
+    spec = inputs.halo_face(512, 1, 2, "lo")
+    _cmp_segments_count(mdt.build_type(spec), obuild(spec), 2, probe_all=False)
