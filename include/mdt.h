@@ -494,6 +494,23 @@ MDT_API int mdt_batch_get_config(mdt_batch b, mdt_batch_config *cfg);
  * NULL. */
 MDT_API int mdt_batch_autotune(mdt_batch b, mdt_stream s, mdt_batch_config *best);
 MDT_API int mdt_batch_launch(mdt_batch b, mdt_stream s, mdt_request *req);
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): as mdt_batch_launch,
+ * but the batch's descriptors, tile prefix and tile counters live in a
+ * fixed device array of the library (128 KiB, one per device, held until
+ * the process ends) instead of the batch's own device buffers, and the call
+ * allocates nothing: no device or host memory, no upload of type tables
+ * (they are resident from the mdt_batch_add_* calls on this device; else
+ * MDT_ERR_STATE).  Descriptors reach the array through small staging
+ * kernels on stream s, followed by the batch kernels.  At most 1024
+ * requests (MDT_ERR_NO_MEM beyond).  The batch's configuration applies,
+ * except that tiles always run in request order (order = 1 is ignored).
+ * The array is shared by every call on the device and keeps the last
+ * call's contents: calls that overlap on one device (on different streams,
+ * or from several threads without ordering) race; calls on one stream are
+ * ordered.  Returns no request: completion is the stream's (record an
+ * event after it). */
+MDT_API int mdt_batch_launch_noalloc(mdt_batch b, mdt_stream s);
 
 /* ---------------------------------------------------------------------
  * Serving: a progress engine that continuously batches pack/unpack

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -86,10 +87,10 @@ __global__ void batch_counter_reset(unsigned long long *counter) { *counter = 0u
 
 namespace {
 
-size_t hdr_bytes() { return 256; }
-size_t desc_off() { return hdr_bytes(); }
-size_t tile_off(size_t cap) { return (desc_off() + cap * sizeof(ReqDesc) + 255) & ~(size_t)255; }
-size_t buf_bytes(size_t cap) { return tile_off(cap) + (cap + 1) * sizeof(int64_t); }
+constexpr size_t hdr_bytes() { return 256; }
+constexpr size_t desc_off() { return hdr_bytes(); }
+constexpr size_t tile_off(size_t cap) { return (desc_off() + cap * sizeof(ReqDesc) + 255) & ~(size_t)255; }
+constexpr size_t buf_bytes(size_t cap) { return tile_off(cap) + (cap + 1) * sizeof(int64_t); }
 
 void release_graph(mdt_batch_s *b)
 {
@@ -467,6 +468,184 @@ int launch(mdt_batch_s *b, hipStream_t s, bool track = true)
 
 bool valid_batch(mdt_batch b) { return b && b->magic == BATCH_MAGIC; }
 
+// ---- launches that allocate nothing ----------------------------------------
+//
+// mdt_batch_launch_noalloc runs a batch through a file-scope device array
+// instead of the batch's own device buffers: the same layout (header,
+// descriptors, tile prefix) for at most NOALLOC_MAX_REQ requests, plus the
+// two tile counters.  Descriptors get there through staging kernels whose
+// arguments carry them (STAGE_N per launch), so the call makes no host to
+// device copy and no allocation.  Every call on a device shares that
+// device's array.
+
+constexpr int64_t NOALLOC_MAX_REQ = 1024;
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)128 << 10;
+constexpr size_t NOALLOC_CTR_OFF = NOALLOC_SCRATCH_BYTES - 256;
+constexpr int STAGE_N = 16;
+
+struct StageChunk {
+    int64_t first;        // index of the chunk's first descriptor
+    int64_t n;            // descriptors in the chunk
+    int64_t tile_end;     // the prefix entry after the chunk's last request (last chunk), else -1
+    int64_t with_header;  // the chunk also writes the header
+    BatchHeader H;
+    ReqDesc d[STAGE_N];
+    int64_t tile0[STAGE_N];
+};
+
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace mdt {
+// one workgroup copies a chunk of descriptors (and the header) into place
+__global__ __launch_bounds__(256) void noalloc_stage_kernel(uint8_t *buf, StageChunk c)
+{
+    const int t = threadIdx.x;
+    uint64_t *R = (uint64_t *)(buf + desc_off());
+    int64_t *tile0 = (int64_t *)(buf + tile_off((size_t)NOALLOC_MAX_REQ));
+    constexpr int W = (int)(sizeof(ReqDesc) / 8);
+    for (int k = t; k < (int)c.n * W; k += 256) R[(size_t)c.first * W + k] = ((const uint64_t *)c.d)[k];
+    for (int i = t; i < (int)c.n; i += 256) tile0[c.first + i] = c.tile0[i];
+    if (t == 0 && c.tile_end >= 0) tile0[c.first + c.n] = c.tile_end;
+    if (c.with_header)
+        for (int w = t; w < (int)(sizeof(BatchHeader) / 8); w += 256)
+            ((uint64_t *)buf)[w] = ((const uint64_t *)&c.H)[w];
+}
+}  // namespace mdt
+
+namespace {
+
+static_assert(sizeof(ReqDesc) % 8 == 0 && sizeof(BatchHeader) % 8 == 0, "staged as 8-byte words");
+static_assert(sizeof(StageChunk) <= 2048, "a chunk travels as kernel arguments");
+
+struct NoallocDevice {
+    uint8_t *ptr = nullptr;  // this device's copy of `scratch`
+    int ncu = 0;
+    bool ready = false;
+};
+std::mutex g_noalloc_mu;
+NoallocDevice g_noalloc[64];
+
+// The device address of `scratch` on the current device, looked up once per
+// device (each device holds its own copy of the array).
+int noalloc_scratch(int dev, NoallocDevice **out)
+{
+    if (dev < 0 || dev >= 64) return MDT_ERR_ARG;
+    std::lock_guard<std::mutex> g(g_noalloc_mu);
+    NoallocDevice &d = g_noalloc[dev];
+    if (!d.ready) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_hip_error((int)e);
+            return MDT_ERR_HIP;
+        }
+        if (hipDeviceGetAttribute(&d.ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || d.ncu <= 0)
+            d.ncu = 256;
+        d.ptr = static_cast<uint8_t *>(p);
+        d.ready = true;
+    }
+    *out = &d;
+    return MDT_SUCCESS;
+}
+
+int launch_noalloc(mdt_batch_s *b, hipStream_t s)
+{
+    static_assert(NOALLOC_CTR_OFF >= buf_bytes(NOALLOC_MAX_REQ), "counters after the descriptor area");
+    if ((int64_t)b->reqs.size() > NOALLOC_MAX_REQ) return MDT_ERR_NO_MEM;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_hip_error((int)e);
+        return MDT_ERR_HIP;
+    }
+    NoallocDevice *nd = nullptr;
+    int rc = noalloc_scratch(dev, &nd);
+    if (rc) return rc;
+    // every request's layout tables must already be on this device (they
+    // are uploaded when a request is added): nothing is uploaded here
+    for (const BatchReq &r : b->reqs) {
+        DeviceTables *D = nullptr;
+        rc = device_tables_resident(r.type->comp.get(), &D);
+        if (rc) return rc;
+        if ((uint64_t)(uintptr_t)D->d_lay != r.d.lay) return MDT_ERR_STATE;
+        if (r.type2) {
+            rc = device_tables_resident(r.type2->comp.get(), &D);
+            if (rc) return rc;
+        }
+    }
+    if (b->cfg.policy == 3) return enqueue_single(b, s);  // per-request kernels use no scratch
+    const int64_t T = b->cfg.tile_chunks;
+    BatchHeader H{};
+    H.tile_chunks = T;
+    int32_t lds_dir[2] = {0, 0}, body_dir[2] = {0, 0};
+    int64_t packed = 0;
+    for (const BatchReq &r : b->reqs) {
+        const int dir = r.d.unpack;
+        H.nreq_dir[dir]++;
+        H.ntiles_dir[dir] += (r.d.nchunks + T - 1) / T;
+        lds_dir[dir] = std::max(lds_dir[dir], r.lds);
+        body_dir[dir] |= r.d.body;
+        if (!dir && !r.type2) packed += r.d.nbytes;
+    }
+    H.keep_packed = packed <= KEEP_PACKED_MAX ? 1 : 0;
+    if (H.ntiles_dir[0] + H.ntiles_dir[1] > INT32_MAX) return MDT_ERR_COUNT;
+    // stage the descriptors, pack requests first, in chunks
+    StageChunk c{};
+    c.H = H;
+    c.with_header = 1;
+    int64_t k = 0, acc = 0;
+    const int64_t nreq = (int64_t)b->reqs.size();
+    auto flush = [&](bool last) {
+        c.tile_end = last ? acc : -1;
+        hipLaunchKernelGGL(noalloc_stage_kernel, dim3(1), dim3(256), 0, s, nd->ptr, c);
+        c.first += c.n;
+        c.n = 0;
+        c.with_header = 0;
+    };
+    for (int dir = 0; dir < 2; dir++)
+        for (const BatchReq &r : b->reqs) {
+            if (r.d.unpack != dir) continue;
+            c.d[c.n] = r.d;
+            c.tile0[c.n] = acc;
+            acc += (r.d.nchunks + T - 1) / T;
+            c.n++;
+            k++;
+            if (c.n == STAGE_N || k == nreq) flush(k == nreq);
+        }
+    if (nreq == 0) flush(true);
+    const BatchHeader *Hd = (const BatchHeader *)nd->ptr;
+    const ReqDesc *R = (const ReqDesc *)(nd->ptr + desc_off());
+    const int64_t *tile0 = (const int64_t *)(nd->ptr + tile_off((size_t)NOALLOC_MAX_REQ));
+    unsigned long long *ctr = (unsigned long long *)(nd->ptr + NOALLOC_CTR_OFF);
+    for (int dir = 0; dir < 2; dir++) {
+        const int64_t nt = H.ntiles_dir[dir];
+        if (nt == 0) continue;
+        int64_t g = b->cfg.wgs_per_cu > 0 ? std::min<int64_t>((int64_t)nd->ncu * b->cfg.wgs_per_cu, nt) : nt;
+        const dim3 grid((unsigned)std::max<int64_t>(1, g));
+        const size_t lds = (size_t)lds_dir[dir];
+        if (b->cfg.policy == 1) {
+            // the dynamic split's counter starts at zero (a kernel, not a memset)
+            hipLaunchKernelGGL(batch_counter_reset, dim3(1), dim3(1), 0, s, ctr + dir);
+            if (dir) launch_batch_dir<1, 1>(grid, lds, s, Hd, R, tile0, nullptr, ctr + dir, body_dir[dir]);
+            else launch_batch_dir<1, 0>(grid, lds, s, Hd, R, tile0, nullptr, ctr + dir, body_dir[dir]);
+        } else if (b->cfg.policy == 2 && (int64_t)grid.x == nt) {
+            if (dir) launch_batch_dir<2, 1>(grid, lds, s, Hd, R, tile0, nullptr, ctr + dir, body_dir[dir]);
+            else launch_batch_dir<2, 0>(grid, lds, s, Hd, R, tile0, nullptr, ctr + dir, body_dir[dir]);
+        } else {
+            if (dir) launch_batch_dir<0, 1>(grid, lds, s, Hd, R, tile0, nullptr, ctr + dir, body_dir[dir]);
+            else launch_batch_dir<0, 0>(grid, lds, s, Hd, R, tile0, nullptr, ctr + dir, body_dir[dir]);
+        }
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_hip_error((int)e);
+        return MDT_ERR_HIP;
+    }
+    return MDT_SUCCESS;
+}
+
 bool valid_cfg(const mdt_batch_config &c)
 {
     bool tc = c.tile_chunks == 256 || c.tile_chunks == 512 || c.tile_chunks == 1024 || c.tile_chunks == 2048 ||
@@ -681,6 +860,12 @@ MDT_API int mdt_batch_launch(mdt_batch b, mdt_stream s, mdt_request *req)
     int rc = launch(b, s->s);
     if (rc) return rc;
     return request_from_stream(s->s, req, s);
+}
+
+MDT_API int mdt_batch_launch_noalloc(mdt_batch b, mdt_stream s)
+{
+    if (!valid_batch(b) || !s || s->magic != STREAM_MAGIC) return MDT_ERR_ARG;
+    return launch_noalloc(b, s->s);
 }
 
 MDT_API int mdt_batch_autotune(mdt_batch b, mdt_stream s, mdt_batch_config *best)

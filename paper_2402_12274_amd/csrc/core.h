@@ -161,6 +161,8 @@ int build_segment_table(Compiled *c);
 
 // device.hip
 int device_tables(Compiled *c, DeviceTables **out);  // upload on first use per device
+// the tables already resident on the current device; MDT_ERR_STATE if none (no upload)
+int device_tables_resident(Compiled *c, DeviceTables **out);
 void free_device_tables(DeviceTables *d);
 void set_hip_error(int e);
 

@@ -61,6 +61,22 @@ void free_device_tables(DeviceTables *d)
     if (d->device >= 0 && cur >= 0 && cur != d->device) (void)hipSetDevice(cur);
 }
 
+int device_tables_resident(Compiled *c, DeviceTables **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0) {
+        set_hip_error((int)e);
+        return MDT_ERR_HIP;
+    }
+    std::lock_guard<std::mutex> g(c->dev_mu);
+    if ((size_t)dev < c->dev.size() && c->dev[dev]) {
+        *out = c->dev[dev].get();
+        return MDT_SUCCESS;
+    }
+    return MDT_ERR_STATE;
+}
+
 int device_tables(Compiled *c, DeviceTables **out)
 {
     int dev = -1;

@@ -142,6 +142,7 @@ _SIGS = {
     "mdt_batch_get_config": ([_P, C.POINTER(BatchConfig)], _INT),
     "mdt_batch_autotune": ([_P, _P, C.POINTER(BatchConfig)], _INT),
     "mdt_batch_launch": ([_P, _P, C.POINTER(_P)], _INT),
+    "mdt_batch_launch_noalloc": ([_P, _P], _INT),
     "mdt_server_create": ([C.POINTER(ServerConfig), C.POINTER(_P)], _INT),
     "mdt_server_free": ([C.POINTER(_P)], _INT),
     "mdt_server_submit_pack": ([_P, _P, _I64, _P, _I64, _I64, C.POINTER(_P)], _INT),
@@ -680,6 +681,12 @@ class Batch:
         req = Request() if want_request else None
         check(_lib.mdt_batch_launch(self.handle, stream.h, C.byref(req.handle) if req else None), "batch_launch")
         return req
+
+
+    def launch_noalloc(self, stream: Stream):
+        """mdt_batch_launch_noalloc: the launch through the library's fixed
+        device array (no allocation)."""
+        check(_lib.mdt_batch_launch_noalloc(self.handle, stream.h), "batch_launch_noalloc")
 
 
 def config_dict(cfg: BatchConfig) -> dict:
