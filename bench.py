@@ -138,6 +138,8 @@ def parse(argv=None):
                     help="batched mode: skip the per-request comparison (profiling runs: the timed launches are then "
                          "the trace's last ones)")
     ap.add_argument("--cpu-seconds", type=float, default=8.0, help="seconds of each CPU-baseline leg")
+    ap.add_argument("--no-ceiling", action="store_true",
+                    help="skip the copy-ceiling measurement (profiling runs: the timed launches stay the trace's last)")
     return ap.parse_args(argv)
 
 
@@ -921,8 +923,10 @@ def main():
     gpu_dst = S["dsts"][r_last].cpu().numpy()
     del S
     torch.cuda.empty_cache()
-    log("copy ceiling")
-    ceiling = copy_ceiling(torch, mdt)
+    ceiling = None
+    if not args.no_ceiling:
+        log("copy ceiling")
+        ceiling = copy_ceiling(torch, mdt)
     out = {
         "metric": METRIC,
         "value": round(value, 2),

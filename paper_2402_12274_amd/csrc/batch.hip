@@ -41,7 +41,22 @@ struct BatchReq {
     ReqDesc d;
     int32_t lds;      // dynamic LDS the request's body needs
     TypeNode *type2;  // copy: the destination type (retained), else NULL
+    int64_t mean_run; // packed bytes per typed run of the request's type
 };
+
+// Chunks per tile of a request.  In typed-address order a request of short
+// runs gets proportionally shorter tiles (down to a quarter), so that tiles
+// of requests whose runs share cache lines -- the width-1 and width-4 faces
+// of one side of a halo, 8-byte and 32-byte blocks in the same 128-byte
+// lines -- cover the same rows: sorted by typed address they run side by
+// side on one XCD and the second access to a line hits its L2.
+int64_t tile_chunks_of(const mdt_batch_config &cfg, const BatchReq &r)
+{
+    const int64_t T = cfg.tile_chunks;
+    if (!cfg.order || r.mean_run >= 32) return T;
+    const int64_t t = T * std::max<int64_t>(r.mean_run, 8) / 32;
+    return std::max<int64_t>(64, t / 64 * 64);
+}
 
 struct mdt_batch_s {
     uint32_t magic = BATCH_MAGIC;
@@ -195,7 +210,7 @@ int build_order(mdt_batch_s *b, const ReqDesc *D, const int64_t *tile0, const Ba
             const ReqDesc &d = D[k];
             const DevLayout &L = byk[(size_t)k]->type->comp->host;
             for (int64_t t = tile0[k]; t < tile0[k + 1]; t++) {
-                int64_t p = (t - tile0[k]) * T * 16 - d.head;
+                int64_t p = (t - tile0[k]) * d.tc * 16 - d.head;
                 if (p < 0) p = 0;
                 const uint64_t sp = (uint64_t)(d.off + p);
                 Loc l;
@@ -262,10 +277,11 @@ int stage(mdt_batch_s *b, hipStream_t s)
         for (size_t i = 0; i < b->reqs.size(); i++) {
             if (b->reqs[i].d.unpack != dir) continue;
             D[k] = b->reqs[i].d;
+            D[k].tc = tile_chunks_of(b->cfg, b->reqs[i]);
             b->lds_dir[dir] = std::max(b->lds_dir[dir], b->reqs[i].lds);
             b->body_dir[dir] |= D[k].body;
             tile0[k] = acc;
-            acc += (b->reqs[i].d.nchunks + T - 1) / T;
+            acc += (D[k].nchunks + D[k].tc - 1) / D[k].tc;
             H.nreq_dir[dir]++;
             k++;
         }
@@ -584,7 +600,7 @@ int launch_noalloc(mdt_batch_s *b, hipStream_t s)
     for (const BatchReq &r : b->reqs) {
         const int dir = r.d.unpack;
         H.nreq_dir[dir]++;
-        H.ntiles_dir[dir] += (r.d.nchunks + T - 1) / T;
+        H.ntiles_dir[dir] += (r.d.nchunks + T - 1) / T;  // request order: every request at T
         lds_dir[dir] = std::max(lds_dir[dir], r.lds);
         body_dir[dir] |= r.d.body;
         if (!dir && !r.type2) packed += r.d.nbytes;
@@ -608,6 +624,7 @@ int launch_noalloc(mdt_batch_s *b, hipStream_t s)
         for (const BatchReq &r : b->reqs) {
             if (r.d.unpack != dir) continue;
             c.d[c.n] = r.d;
+            c.d[c.n].tc = T;
             c.tile0[c.n] = acc;
             acc += (r.d.nchunks + T - 1) / T;
             c.n++;
@@ -676,7 +693,8 @@ int add_req(mdt_batch b, TypeNode *t, const ReqDesc &d, int32_t lds, TypeNode *t
     try {
         retain(t);
         if (t2) retain(t2);
-        b->reqs.push_back({t, d, lds, t2});
+        const int64_t runs = t->comp ? t->comp->nruns : 0;
+        b->reqs.push_back({t, d, lds, t2, runs > 0 ? t->size / runs : INT64_MAX});
     } catch (...) {
         release(t);
         if (t2) release(t2);

@@ -20,6 +20,7 @@ struct ReqDesc {
     int32_t elem1, body;  // BODY_DENSE, BODY_RUNS, BODY_CHUNK or BODY_COPY
     uint64_t lay2;         // copy: the destination's layout program
     int32_t kind2, elem1_2;
+    int64_t tc;            // 16-byte chunks per tile of this request
 };
 
 // Tile bodies a batch kernel carries (a bit set): a kernel compiled for one
@@ -145,7 +146,6 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restric
 {
     extern __shared__ __align__(16) uint8_t lds_dyn[];
     __shared__ int64_t s_t;
-    const int64_t T = H->tile_chunks;
     const bool ordered = H->ordered != 0;
     // this direction's requests [r0, r1) and index range [t_begin, t_end):
     // tiles, or slots of the order table
@@ -178,6 +178,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restric
             A.nbytes = D.nbytes;
             A.head = D.head;
             A.nchunks = D.nchunks;
+            const int64_t T = D.tc;
             A.tile_chunks = T;
             A.elem1 = D.elem1;
             A.keep = (int32_t)H->keep_packed;
