@@ -614,7 +614,10 @@ void thread_main(mdt_server s)
         }
         if (t - last_active < SPIN_US) continue;
         std::unique_lock<std::mutex> q(s->qmu);
-        s->wake.wait_for(q, std::chrono::milliseconds(1), [s] {
+        // a 1 ms nap against the system clock: its timed wait is
+        // pthread_cond_timedwait, which thread checkers follow (the steady
+        // clock's is not intercepted by every ThreadSanitizer runtime)
+        s->wake.wait_until(q, std::chrono::system_clock::now() + std::chrono::milliseconds(1), [s] {
             return s->work.load(std::memory_order_acquire) > 0 || !s->run_thread.load(std::memory_order_acquire);
         });
     }
