@@ -220,9 +220,10 @@ def step_setup(torch, mdt, W, rotate, batched, ms, autotune=True):
             batches.append((bp, bu))
         S["batches"] = batches
         if autotune:
-            bp0, bu0 = batches[0]
-            S["tuned"] = {"pack": mdt.config_dict(bp0.autotune(ms)), "unpack": mdt.config_dict(bu0.autotune(ms))}
-            set_step_config(S, bp0.get_config(), bu0.get_config())
+            # each direction tuned over all rotating copies (inputs as the timed steps see them)
+            cp = mdt.autotune_set([bp for bp, _ in batches], ms)
+            cu = mdt.autotune_set([bu for _, bu in batches], ms)
+            S["tuned"] = {"pack": mdt.config_dict(cp), "unpack": mdt.config_dict(cu)}
     return S
 
 

@@ -493,6 +493,18 @@ MDT_API int mdt_batch_get_config(mdt_batch b, mdt_batch_config *cfg);
  * overwritten with the same bytes), and keep the fastest.  *best may be
  * NULL. */
 MDT_API int mdt_batch_autotune(mdt_batch b, mdt_stream s, mdt_batch_config *best);
+/* Tune n batches of the same shape together (say the copies of a buffer a
+ * caller rotates through, so every candidate is timed on inputs as they
+ * run, out of cache): each candidate runs all n in turn, five times after
+ * a warm-up, the median decides, and all n take the winner.  mdt_batch_autotune
+ * is the n = 1 case.  With the environment variable MDT_AUTOTUNE_CACHE
+ * naming a file, the choice is stored there under the batch's shape (per
+ * request: direction, tile body, layout kind, type size, runs per element
+ * and packed bytes to a power of two; the device's compute units; the
+ * library version), and a later tuning of the same shape reads it back
+ * instead of timing.  The file is a JSON object, one entry per line; it is
+ * rewritten through a temporary file and a rename. */
+MDT_API int mdt_batch_autotune_set(int n, mdt_batch *batches, mdt_stream s, mdt_batch_config *best);
 MDT_API int mdt_batch_launch(mdt_batch b, mdt_stream s, mdt_request *req);
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid allocation): as mdt_batch_launch,

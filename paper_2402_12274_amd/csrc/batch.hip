@@ -21,7 +21,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <mutex>
+#include <string>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -707,6 +710,182 @@ int add_req(mdt_batch b, TypeNode *t, const ReqDesc &d, int32_t lds, TypeNode *t
 
 }  // namespace
 
+namespace {
+
+// ---- the autotuner and its cache ----------------------------------------
+//
+// Candidates: tile size x workgroups per CU x split policy x tile order x
+// graph replay (the grid below).  Each candidate runs the set of batches in
+// turn -- a caller's rotating copies, so the timing sees the inputs as they
+// run, out of cache -- once to warm up (uploads, graph capture) and then
+// TUNE_REPS times; the median set time decides.  With MDT_AUTOTUNE_CACHE
+// naming a file, a choice is kept there under the batch's shape and reused
+// (no timing) by later tunings of the same shape on the same kind of device.
+
+constexpr int TUNE_REPS = 5;
+
+uint64_t fnv1a(uint64_t h, uint64_t v)
+{
+    for (int i = 0; i < 8; i++) {
+        h ^= (v >> (8 * i)) & 0xff;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// The shape of a batch: per request its direction, body, layout kind, type
+// size, runs per element and packed bytes (to a power of two), in request
+// order; plus the device's compute units and the library version.
+std::string shape_key(mdt_batch_s *b, int ncu)
+{
+    uint64_t h = 1469598103934665603ull;
+    h = fnv1a(h, (uint64_t)mdt_version());
+    h = fnv1a(h, (uint64_t)ncu);
+    for (const BatchReq &r : b->reqs) {
+        h = fnv1a(h, ((uint64_t)r.d.unpack << 48) | ((uint64_t)r.d.body << 32) | (uint64_t)(uint32_t)r.d.kind);
+        h = fnv1a(h, (uint64_t)r.type->size);
+        h = fnv1a(h, (uint64_t)(r.type->comp ? r.type->comp->nruns : 0));
+        h = fnv1a(h, (uint64_t)(64 - __builtin_clzll((uint64_t)r.d.nbytes | 1)));
+        if (r.type2) h = fnv1a(h, (uint64_t)r.type2->size);
+    }
+    char buf[40];
+    std::snprintf(buf, sizeof buf, "%016llx-%zu", (unsigned long long)h, b->reqs.size());
+    return buf;
+}
+
+// Cache file: one entry per line, `"key": [tile_chunks, wgs_per_cu, policy,
+// use_graph, order]`, inside one JSON object.
+std::mutex g_cache_mu;
+
+bool cache_lookup(const char *path, const std::string &key, mdt_batch_config *c)
+{
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[256];
+    bool found = false;
+    const std::string want = "\"" + key + "\"";
+    while (!found && std::fgets(line, sizeof line, f)) {
+        const char *p = std::strstr(line, want.c_str());
+        if (!p) continue;
+        mdt_batch_config x{};
+        if (std::sscanf(p + want.size(), " : [%d, %d, %d, %d, %d]", &x.tile_chunks, &x.wgs_per_cu, &x.policy,
+                        &x.use_graph, &x.order) == 5 &&
+            valid_cfg(x)) {
+            *c = x;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, const mdt_batch_config &c)
+{
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    std::vector<std::string> keep;
+    if (FILE *f = std::fopen(path, "r")) {
+        char line[256];
+        const std::string own = "\"" + key + "\"";
+        while (std::fgets(line, sizeof line, f)) {
+            std::string l(line);
+            if (l.find("\": [") == std::string::npos || l.find(own) != std::string::npos) continue;
+            while (!l.empty() && (l.back() == '\n' || l.back() == ',' || l.back() == ' ')) l.pop_back();
+            keep.push_back(l);
+        }
+        std::fclose(f);
+    }
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "  \"%s\": [%d, %d, %d, %d, %d]", key.c_str(), c.tile_chunks, c.wgs_per_cu,
+                  c.policy, c.use_graph, c.order);
+    keep.push_back(buf);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fputs("{\n", f);
+    for (size_t i = 0; i < keep.size(); i++) std::fprintf(f, "%s%s\n", keep[i].c_str(), i + 1 < keep.size() ? "," : "");
+    std::fputs("}\n", f);
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);  // replaces the file in one step
+}
+
+int autotune_set(int n, mdt_batch *bs, hipStream_t s, mdt_batch_config *best)
+{
+    int rc = init_device(bs[0]);
+    if (rc) return rc;
+    const char *path = std::getenv("MDT_AUTOTUNE_CACHE");
+    std::string key;
+    if (path && *path) {
+        key = shape_key(bs[0], bs[0]->ncu);
+        mdt_batch_config c{};
+        if (cache_lookup(path, key, &c)) {
+            for (int i = 0; i < n; i++) mdt_batch_set_config(bs[i], &c);
+            if (best) *best = c;
+            return MDT_SUCCESS;
+        }
+    }
+    std::vector<mdt_batch_config> keep((size_t)n);
+    for (int i = 0; i < n; i++) keep[(size_t)i] = bs[i]->cfg;
+    mdt_batch_config win = keep[0];
+    float win_ms = 1e30f;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return MDT_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return MDT_ERR_HIP;
+    }
+    const int tiles[] = {256, 1024, 4096};
+    const int occ[] = {0, 2, 4, 8};  // 0: one workgroup per tile
+    auto run_set = [&]() {
+        for (int i = 0; i < n; i++) {
+            int r = launch(bs[i], s);
+            if (r) return r;
+        }
+        return (int)MDT_SUCCESS;
+    };
+    for (int graph = 0; graph < 2 && !rc; graph++)
+        for (int ord = 0; ord < 2 && !rc; ord++)
+            for (int policy = 0; policy < 4 && !rc; policy++)
+                for (int tc : tiles)
+                    for (int w : occ) {
+                        if (rc) break;
+                        if (policy == 1 && w == 0) continue;  // nothing to balance with a workgroup per tile
+                        if (policy == 2 && w != 0) continue;  // the loop-free kernel takes one tile per workgroup
+                        // single-request kernels: their own tiles, no order
+                        if (policy == 3 && (w != 0 || tc != 1024 || ord != 0)) continue;
+                        mdt_batch_config c{tc, w, policy, graph, ord};
+                        for (int i = 0; i < n; i++) mdt_batch_set_config(bs[i], &c);
+                        rc = run_set();  // warm-up (uploads, graph capture)
+                        if (rc) break;
+                        float ms[TUNE_REPS];
+                        for (int k = 0; k < TUNE_REPS && !rc; k++) {
+                            (void)hipEventRecord(e0, s);
+                            rc = run_set();
+                            (void)hipEventRecord(e1, s);
+                            (void)hipEventSynchronize(e1);
+                            (void)hipEventElapsedTime(&ms[k], e0, e1);
+                        }
+                        if (rc) break;
+                        std::sort(ms, ms + TUNE_REPS);
+                        if (ms[TUNE_REPS / 2] < win_ms) {
+                            win_ms = ms[TUNE_REPS / 2];
+                            win = c;
+                        }
+                    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+        for (int i = 0; i < n; i++) mdt_batch_set_config(bs[i], &keep[(size_t)i]);
+        return rc;
+    }
+    for (int i = 0; i < n; i++) mdt_batch_set_config(bs[i], &win);
+    if (path && *path) cache_store(path, key, win);
+    if (best) *best = win;
+    return MDT_SUCCESS;
+}
+
+}  // namespace
+
 namespace mdt {
 // used by the serving loop
 int batch_launch_internal(mdt_batch b, hipStream_t s) { return launch(b, s, false); }
@@ -886,54 +1065,18 @@ MDT_API int mdt_batch_launch_noalloc(mdt_batch b, mdt_stream s)
     return launch_noalloc(b, s->s);
 }
 
+MDT_API int mdt_batch_autotune_set(int n, mdt_batch *batches, mdt_stream s, mdt_batch_config *best)
+{
+    if (n <= 0 || !batches || !s || s->magic != STREAM_MAGIC) return MDT_ERR_ARG;
+    for (int i = 0; i < n; i++)
+        if (!valid_batch(batches[i])) return MDT_ERR_ARG;
+    return autotune_set(n, batches, s->s, best);
+}
+
 MDT_API int mdt_batch_autotune(mdt_batch b, mdt_stream s, mdt_batch_config *best)
 {
     if (!valid_batch(b) || !s || s->magic != STREAM_MAGIC) return MDT_ERR_ARG;
-    const mdt_batch_config keep = b->cfg;
-    mdt_batch_config win = keep;
-    float win_ms = 1e30f;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MDT_ERR_HIP;
-    const int tiles[] = {256, 1024, 4096};
-    const int occ[] = {0, 2, 4, 8};  // 0: one workgroup per tile
-    int rc = MDT_SUCCESS;
-    for (int graph = 0; graph < 2 && !rc; graph++)
-        for (int ord = 0; ord < 2 && !rc; ord++)
-            for (int policy = 0; policy < 4 && !rc; policy++)
-                for (int tc : tiles)
-                    for (int w : occ) {
-                        if (policy == 1 && w == 0) continue;  // nothing to balance with a workgroup per tile
-                        if (policy == 2 && w != 0) continue;  // the loop-free kernel takes one tile per workgroup
-                        // single-request kernels: their own tiles, no order
-                        if (policy == 3 && (w != 0 || tc != 1024 || ord != 0)) continue;
-                        mdt_batch_config c{tc, w, policy, graph, ord};
-                        mdt_batch_set_config(b, &c);
-                        rc = launch(b, s->s);  // warm-up (uploads, graph capture)
-                        if (rc) break;
-                        float ms[3];
-                        for (int k = 0; k < 3 && !rc; k++) {
-                            (void)hipEventRecord(e0, s->s);
-                            rc = launch(b, s->s);
-                            (void)hipEventRecord(e1, s->s);
-                            (void)hipEventSynchronize(e1);
-                            (void)hipEventElapsedTime(&ms[k], e0, e1);
-                        }
-                        if (rc) break;
-                        std::sort(ms, ms + 3);
-                        if (ms[1] < win_ms) {
-                            win_ms = ms[1];
-                            win = c;
-                        }
-                    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (rc) {
-        mdt_batch_set_config(b, &keep);
-        return rc;
-    }
-    mdt_batch_set_config(b, &win);
-    if (best) *best = win;
-    return MDT_SUCCESS;
+    return autotune_set(1, &b, s->s, best);
 }
 
 }  // extern "C"

@@ -141,6 +141,7 @@ _SIGS = {
     "mdt_batch_set_config": ([_P, C.POINTER(BatchConfig)], _INT),
     "mdt_batch_get_config": ([_P, C.POINTER(BatchConfig)], _INT),
     "mdt_batch_autotune": ([_P, _P, C.POINTER(BatchConfig)], _INT),
+    "mdt_batch_autotune_set": ([_INT, C.POINTER(_P), _P, C.POINTER(BatchConfig)], _INT),
     "mdt_batch_launch": ([_P, _P, C.POINTER(_P)], _INT),
     "mdt_batch_launch_noalloc": ([_P, _P], _INT),
     "mdt_server_create": ([C.POINTER(ServerConfig), C.POINTER(_P)], _INT),
@@ -687,6 +688,15 @@ class Batch:
         """mdt_batch_launch_noalloc: the launch through the library's fixed
         device array (no allocation)."""
         check(_lib.mdt_batch_launch_noalloc(self.handle, stream.h), "batch_launch_noalloc")
+
+
+def autotune_set(batches, stream: Stream) -> BatchConfig:
+    """mdt_batch_autotune_set: one configuration for batches of one shape,
+    timed over all of them in turn."""
+    arr = (_P * len(batches))(*[b.handle.value for b in batches])
+    cfg = BatchConfig()
+    check(_lib.mdt_batch_autotune_set(len(batches), arr, stream.h, C.byref(cfg)), "batch_autotune_set")
+    return cfg
 
 
 def config_dict(cfg: BatchConfig) -> dict:

@@ -368,3 +368,56 @@ def test_single_request_policy_graph_follows_requests(env):
         torch.cuda.synchronize()
     assert first_diff(to_host(out2), full) is None
     assert not to_host(out1).any()
+
+
+def test_autotune_set_and_cache(env, tmp_path, monkeypatch):
+    """One configuration tuned over rotating copies is applied to all of
+    them and stored in the cache file under the batch shape; a later tuning
+    of a batch of the same shape reads it back (no timing); the bytes stay
+    the oracle's."""
+    import json
+    import time
+
+    torch, mdt = env
+    note("autotune over rotating copies, cache file")
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("MDT_AUTOTUNE_CACHE", str(cache))
+    spec = inputs.halo_face(128, 2, 2, "lo")
+    t = mdt.build_type(spec)
+    host = inputs.random_bytes(128 ** 3 * 8, seed=81)
+    ref = obuild(spec).pack(host, 0, 1)
+    ms = mdt.Stream(torch.cuda.current_stream().cuda_stream)
+    srcs = [to_dev(host) for _ in range(3)]
+    outs = [zeros_dev(t.size(), 0) for _ in range(3)]
+
+    def batches():
+        bs = []
+        for s, o in zip(srcs, outs):
+            b = mdt.Batch()
+            b.add_pack(s.data_ptr(), 1, t, 0, o.data_ptr(), -1)
+            bs.append(b)
+        return bs
+
+    bs = batches()
+    cfg = mdt.autotune_set(bs, ms)
+    assert all(mdt.config_dict(b.get_config()) == mdt.config_dict(cfg) for b in bs)
+    entries = json.loads(cache.read_text())
+    assert len(entries) == 1 and list(entries.values())[0] == [cfg.tile_chunks, cfg.wgs_per_cu, cfg.policy,
+                                                               cfg.use_graph, cfg.order]
+    bs2 = batches()
+    t0 = time.perf_counter()
+    cfg2 = bs2[0].autotune(ms)  # same shape: read back
+    assert time.perf_counter() - t0 < 0.05
+    assert mdt.config_dict(cfg2) == mdt.config_dict(cfg)
+    for o in outs:
+        o.fill_(0)
+    for b in bs2[:1] + bs[1:]:
+        b.launch(ms)
+    torch.cuda.synchronize()
+    for o in outs:
+        assert first_diff(to_host(o), ref) is None
+    # a different shape gets its own entry
+    b3 = mdt.Batch()
+    b3.add_pack(srcs[0].data_ptr(), 1, t, 0, outs[0].data_ptr(), 1000)
+    b3.autotune(ms)
+    assert len(json.loads(cache.read_text())) == 2
