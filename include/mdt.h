@@ -467,6 +467,21 @@ MDT_API int mdt_batch_add_unpack(mdt_batch b, const void *inbuf, mdt_count insiz
 MDT_API int mdt_batch_add_copy(mdt_batch b, const void *src, mdt_count srccount, mdt_type srctype, void *dst,
                                mdt_count dstcount, mdt_type dsttype, mdt_count offset, mdt_count max_bytes,
                                mdt_count *actual);
+/* A relay (the two sides of a transfer through a staging buffer, General
+ * Progress, Background: a message is packed for sending and unpacked where it
+ * lands): bytes [offset, offset + actual) of the packed stream of (srccount
+ * x srctype) at src are packed into the device buffer packed (as
+ * mdt_batch_add_pack) and the same bytes are unpacked from it into the same
+ * stream positions of (dstcount x dsttype) at dst (as mdt_batch_add_unpack),
+ * actual = clamp(srccount*srcsize - offset, 0, max_bytes).  Both results
+ * are those of the pack and the unpack run one after the other; in the
+ * batch a workgroup unpacks each tile right after packing it, so the
+ * packed bytes are read back from the cache and the pair costs one launch.
+ * It runs in the first launch, with the pack requests.  Errors as
+ * mdt_typed_copy; the packed buffer must not overlap src or dst. */
+MDT_API int mdt_batch_add_relay(mdt_batch b, const void *src, mdt_count srccount, mdt_type srctype, void *packed,
+                                void *dst, mdt_count dstcount, mdt_type dsttype, mdt_count offset, mdt_count max_bytes,
+                                mdt_count *actual);
 /* Tuning knobs of the persistent launch.  policy: 0 = static strided split
  * of tiles over workgroups, 1 = dynamic (atomic tile counter), 2 = one tile
  * per workgroup run by a kernel without the tile loop (fewer scalar

@@ -47,6 +47,9 @@ struct BatchReq {
     int64_t mean_run; // packed bytes per typed run of the request's type
 };
 
+// Tile bodies a request needs its direction's kernel to carry.
+int body_bits(const ReqDesc &d) { return d.body | (d.body == BODY_RELAY ? d.pbody | d.ubody : 0); }
+
 // Chunks per tile of a request.  In typed-address order a request of short
 // runs gets proportionally shorter tiles (down to a quarter), so that tiles
 // of requests whose runs share cache lines -- the width-1 and width-4 faces
@@ -282,7 +285,7 @@ int stage(mdt_batch_s *b, hipStream_t s)
             D[k] = b->reqs[i].d;
             D[k].tc = tile_chunks_of(b->cfg, b->reqs[i]);
             b->lds_dir[dir] = std::max(b->lds_dir[dir], b->reqs[i].lds);
-            b->body_dir[dir] |= D[k].body;
+            b->body_dir[dir] |= body_bits(D[k]);
             tile0[k] = acc;
             acc += (D[k].nchunks + D[k].tc - 1) / D[k].tc;
             H.nreq_dir[dir]++;
@@ -352,7 +355,13 @@ int enqueue_single(mdt_batch_s *b, hipStream_t s)
             DeviceTables *D = nullptr;
             int rc = device_tables(r.type->comp.get(), &D);
             if (rc) return rc;
-            if (r.type2) {
+            if (r.d.body == BODY_RELAY) {
+                DeviceTables *D2 = nullptr;
+                rc = device_tables(r.type2->comp.get(), &D2);
+                if (rc) return rc;
+                rc = launch_xfer(D->lay, make_args(r.d.typed, r.d.packed, r.d.off, r.d.nbytes), false, s);
+                if (!rc) rc = launch_xfer(D2->lay, make_args(r.d.typed2, r.d.packed, r.d.off, r.d.nbytes), true, s);
+            } else if (r.type2) {
                 DeviceTables *D2 = nullptr;
                 rc = device_tables(r.type2->comp.get(), &D2);
                 if (rc) return rc;
@@ -605,7 +614,7 @@ int launch_noalloc(mdt_batch_s *b, hipStream_t s)
         H.nreq_dir[dir]++;
         H.ntiles_dir[dir] += (r.d.nchunks + T - 1) / T;  // request order: every request at T
         lds_dir[dir] = std::max(lds_dir[dir], r.lds);
-        body_dir[dir] |= r.d.body;
+        body_dir[dir] |= body_bits(r.d);
         if (!dir && !r.type2) packed += r.d.nbytes;
     }
     H.keep_packed = packed <= KEEP_PACKED_MAX ? 1 : 0;
@@ -1026,6 +1035,63 @@ MDT_API int mdt_batch_add_copy(mdt_batch b, const void *src, mdt_count srccount,
         d.kind2 = Dd->lay.kind;
         d.elem1_2 = offset + n <= Dd->lay.size;
         rc = add_req(b, reinterpret_cast<TypeNode *>(srctype), d, 0, reinterpret_cast<TypeNode *>(dsttype));
+        if (rc) return rc;
+    }
+    *actual = n;
+    return MDT_SUCCESS;
+}
+
+MDT_API int mdt_batch_add_relay(mdt_batch b, const void *src, mdt_count srccount, mdt_type srctype, void *packed,
+                                void *dst, mdt_count dstcount, mdt_type dsttype, mdt_count offset, mdt_count max_bytes,
+                                mdt_count *actual)
+{
+    if (!valid_batch(b) || !actual || offset < 0 || max_bytes < -1) return MDT_ERR_ARG;
+    Compiled *Cs, *Cd;
+    DeviceTables *Ds = nullptr, *Dd = nullptr;
+    int64_t total_s, total_d;
+    int rc = prepare(srctype, srccount, &Cs, &Ds, &total_s);
+    if (rc) return rc;
+    rc = prepare(dsttype, dstcount, &Cd, &Dd, &total_d);
+    if (rc) return rc;
+    int64_t n = std::max<int64_t>(0, total_s - offset);
+    if (max_bytes >= 0) n = std::min<int64_t>(n, max_bytes);
+    if (n > std::max<int64_t>(0, total_d - offset)) return MDT_ERR_TRUNCATE;
+    rc = check_unpack_overlap(Cd, dstcount);
+    if (rc) return rc;
+    if (n > 0 && (!src || !packed || !dst)) return MDT_ERR_ARG;
+    if (n > 0) {
+        XferArgs A = make_args(src, packed, offset, n);
+        A.elem1 = A.off + A.nbytes <= Ds->lay.size;
+        XferArgs U = make_args(dst, packed, offset, n);
+        U.elem1 = U.off + U.nbytes <= Dd->lay.size;
+        int32_t lds_p = 0, lds_u = 0;
+        ReqDesc d{};
+        d.lay = (uint64_t)(uintptr_t)Ds->d_lay;
+        d.typed = A.typed;
+        d.packed = A.packed;
+        d.off = A.off;
+        d.nbytes = A.nbytes;
+        d.head = A.head;
+        d.nchunks = A.nchunks;
+        d.unpack = 0;
+        d.kind = Ds->lay.kind;
+        d.elem1 = A.elem1;
+        d.body = BODY_RELAY;
+        d.lay2 = (uint64_t)(uintptr_t)Dd->d_lay;
+        d.kind2 = Dd->lay.kind;
+        d.elem1_2 = U.elem1;
+        d.typed2 = U.typed;
+        d.pbody = body_of(Ds->lay, A, false, &lds_p);
+        // the unpack side reads back only its own tile's packed chunks: the
+        // record view's unpack stages packed bytes of neighbouring records,
+        // which other workgroups may not have packed yet, so it is not used
+        d.ubody = body_of(Dd->lay, U, true, &lds_u);
+        if (d.ubody == BODY_DENSE) {
+            d.ubody = use_runs(Dd->lay) ? BODY_RUNS : BODY_CHUNK;
+            lds_u = d.ubody == BODY_RUNS ? (int32_t)sizeof(RunsCache) : 0;
+        }
+        rc = add_req(b, reinterpret_cast<TypeNode *>(srctype), d, std::max(lds_p, lds_u),
+                     reinterpret_cast<TypeNode *>(dsttype));
         if (rc) return rc;
     }
     *actual = n;

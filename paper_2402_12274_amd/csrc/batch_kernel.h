@@ -18,9 +18,11 @@ struct ReqDesc {
     int64_t off, nbytes, head, nchunks;
     int32_t unpack, kind;
     int32_t elem1, body;  // BODY_DENSE, BODY_RUNS, BODY_CHUNK or BODY_COPY
-    uint64_t lay2;         // copy: the destination's layout program
+    uint64_t lay2;         // copy, relay: the destination's layout program
     int32_t kind2, elem1_2;
     int64_t tc;            // 16-byte chunks per tile of this request
+    const uint8_t *typed2; // relay: the destination origin
+    int32_t pbody, ubody;  // relay: tile bodies of its pack and its unpack
 };
 
 // Tile bodies a batch kernel carries (a bit set): a kernel compiled for one
@@ -31,6 +33,7 @@ constexpr int BODY_RUNS = 2;   // run tables, LDS-cached group slice
 constexpr int BODY_CHUNK = 4;  // chunk path
 constexpr int BODY_ALL = 7;
 constexpr int BODY_COPY = 8;   // typed copy (runs with the pack direction)
+constexpr int BODY_RELAY = 16; // pack, then unpack of the same packed bytes (runs with the pack direction)
 
 // Descriptors are stored pack requests first, so each direction's tiles
 // form one range: [0, ntiles_dir[0]) for pack, then unpack.
@@ -57,6 +60,22 @@ template <int UNPACK, int BODY>
 __device__ __forceinline__ void run_tile(const DevLayout &L, const XferArgs &A, int body, int kind, int64_t c0,
                                          int64_t cend, uint8_t *lds_dyn, const ReqDesc &D)
 {
+    if ((BODY & BODY_RELAY) && body == BODY_RELAY) {
+        // the tile's chunks are packed, then unpacked from the packed buffer
+        // by the same workgroup: after the barrier every lane sees what the
+        // others stored, still in the cache
+        constexpr int SUB = BODY & BODY_ALL;
+        XferArgs P = A;
+        P.keep = 1;
+        run_tile<0, SUB>(L, P, D.pbody, kind, c0, cend, lds_dyn, D);
+        __syncthreads();
+        const DevLayout &L2 = *(const DevLayout *)(const __attribute__((address_space(4))) DevLayout *)(uintptr_t)D.lay2;
+        XferArgs U = A;
+        U.typed = D.typed2;
+        U.elem1 = D.elem1_2;
+        run_tile<1, SUB>(L2, U, D.ubody, D.kind2, c0, cend, lds_dyn, D);
+        return;
+    }
     if ((BODY & BODY_COPY) && body == BODY_COPY) {
         const DevLayout &Ld = *(const DevLayout *)(const __attribute__((address_space(4))) DevLayout *)(uintptr_t)D.lay2;
         CopyArgs C;
@@ -227,7 +246,10 @@ void launch_batch_dir_impl(dim3 grid, size_t lds, hipStream_t s, const BatchHead
 {
 #define MDT_LAUNCH(BODY) hipLaunchKernelGGL((batch_kernel<POLICY, UNPACK, BODY>), grid, dim3(256), lds, s, H, R, \
                                             tile0, order, counter)
-    if (!UNPACK && body == BODY_COPY) MDT_LAUNCH(UNPACK ? BODY_ALL : BODY_COPY);
+    if (!UNPACK && (body & BODY_RELAY)) {
+        if ((body & ~(BODY_RELAY | BODY_CHUNK)) == 0) MDT_LAUNCH(UNPACK ? BODY_ALL : (BODY_RELAY | BODY_CHUNK));
+        else MDT_LAUNCH(UNPACK ? BODY_ALL : (BODY_RELAY | BODY_ALL | BODY_COPY));
+    } else if (!UNPACK && body == BODY_COPY) MDT_LAUNCH(UNPACK ? BODY_ALL : BODY_COPY);
     else if (!UNPACK && (body & BODY_COPY)) MDT_LAUNCH(UNPACK ? BODY_ALL : (BODY_ALL | BODY_COPY));
     else if (body == BODY_DENSE) MDT_LAUNCH(BODY_DENSE);
     else if (body == BODY_RUNS) MDT_LAUNCH(BODY_RUNS);

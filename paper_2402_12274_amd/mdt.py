@@ -138,6 +138,7 @@ _SIGS = {
     "mdt_batch_add_pack": ([_P, _P, _I64, _P, _I64, _P, _I64, _I64P], _INT),
     "mdt_batch_add_unpack": ([_P, _P, _I64, _P, _I64, _P, _I64, _I64P], _INT),
     "mdt_batch_add_copy": ([_P, _P, _I64, _P, _P, _I64, _P, _I64, _I64, _I64P], _INT),
+    "mdt_batch_add_relay": ([_P, _P, _I64, _P, _P, _P, _I64, _P, _I64, _I64, _I64P], _INT),
     "mdt_batch_set_config": ([_P, C.POINTER(BatchConfig)], _INT),
     "mdt_batch_get_config": ([_P, C.POINTER(BatchConfig)], _INT),
     "mdt_batch_autotune": ([_P, _P, C.POINTER(BatchConfig)], _INT),
@@ -662,6 +663,14 @@ class Batch:
         n = C.c_int64()
         check(_lib.mdt_batch_add_copy(self.handle, _P(src), srccount, srctype.h, _P(dst), dstcount, dsttype.h,
                                       offset, max_bytes, C.byref(n)), "batch_add_copy")
+        self._keep.extend((srctype, dsttype))
+        return n.value
+
+    def add_relay(self, src: int, srccount: int, srctype: Type, packed: int, dst: int, dstcount: int, dsttype: Type,
+                  offset: int = 0, max_bytes: int = -1) -> int:
+        n = C.c_int64()
+        check(_lib.mdt_batch_add_relay(self.handle, _P(src), srccount, srctype.h, _P(packed), _P(dst), dstcount,
+                                       dsttype.h, offset, max_bytes, C.byref(n)), "batch_add_relay")
         self._keep.extend((srctype, dsttype))
         return n.value
 
