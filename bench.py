@@ -25,8 +25,11 @@ the same JSON line:
 Other workloads (--workload): particles (struct records x 4M), hindexed (1M
 irregular blocks in 2 GiB), contig (1 GiB contiguous), rows (an interior
 block of an 8192^2 float64 matrix), darray (one rank's block-cyclic share of
-a 512^3 float64 array), small (the 1024-element vector), serve, batch4096
-and copy (periodic halo self-exchange by typed copy).  --mode batched (the
+a 512^3 float64 array), small (the 1024-element vector), serve, batch4096,
+chunked (1 MiB byte ranges of the particle records and of the hindexed
+layout, batched and one launch per range, beside the whole transfer; also
+part of the default run as "chunked_1MiB") and copy (periodic halo
+self-exchange by typed copy).  --mode batched (the
 default) runs each direction of a step as one batched launch (autotuned);
 --mode plain launches once per request.
 
@@ -67,8 +70,7 @@ GiB = 1 << 30
 
 # the sources that decide what the kernels execute: kernel bodies, the
 # layout program and its tables, launch selection and the batch kernels
-KERNEL_SOURCES = ("batch.hip", "batch_kernel.h", "batch_p0u0.hip", "batch_p0u1.hip", "batch_p1u0.hip",
-                  "batch_p1u1.hip", "batch_p2u0.hip", "batch_p2u1.hip", "compile.cpp", "device.h", "device.hip",
+KERNEL_SOURCES = ("batch.hip", "batch_kernel.h", "batch_variants.hip", "compile.cpp", "device.h", "device.hip",
                   "layout_dev.h", "xfer.h")
 
 
@@ -120,7 +122,7 @@ def parse(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="halo",
                     choices=["halo", "particles", "hindexed", "contig", "rows", "darray", "small", "serve", "batch4096",
-                             "copy"])
+                             "copy", "chunked"])
     ap.add_argument("--no-extras", action="store_true",
                     help="halo: skip the batch4096 and serve blocks of the default run")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of trace per replay")
@@ -424,6 +426,102 @@ def copy_ceiling(torch, mdt, nbytes=4 * GiB, reps=8):
     del a, b
     torch.cuda.empty_cache()
     out["bytes"] = nbytes
+    return out
+
+
+# ---------------------------------------------------------------------------
+# pipelined partial transfers: 1 MiB byte ranges of one request
+
+
+def chunked_block(args, torch, mdt, budget=1 << 20, reps=10):
+    """The particle records and the hindexed layout packed and unpacked in
+    1 MiB byte ranges of their packed streams (126 and 23 ranges: the pieces
+    a pipelined transfer hands on one at a time), as one autotuned batch per
+    direction and as one launch per range, beside the whole transfer in one
+    launch.  Sources of 256 MiB or more rotate over 4 copies.  The ranges'
+    packed bytes are checked equal to the whole pack's and the ranges'
+    unpack equal to the whole unpack's; times are medians of `reps`."""
+    stream = torch.cuda.current_stream()
+    ms = mdt.Stream(stream.cuda_stream)
+    dev = torch.device("cuda:0")
+    out = {"budget_bytes": budget}
+    for name in ("particles", "hindexed"):
+        W = workload(name)
+        (_, spec, count), = W["reqs"]
+        t = mdt.build_type(spec)
+        total = t.size() * count
+        host = inputs.random_bytes(W["src_bytes"], seed=W["seed"])
+        R = 4 if W["src_bytes"] >= (1 << 28) else 1
+        srcs = [torch.from_numpy(host).to(dev) for _ in range(R)]
+        del host
+        whole_p = torch.empty(total, dtype=torch.uint8, device=dev)
+        parts_p = [torch.empty(total, dtype=torch.uint8, device=dev) for _ in range(R)]
+        whole_d = torch.zeros(W["src_bytes"], dtype=torch.uint8, device=dev)
+        parts_d = [torch.zeros(W["src_bytes"], dtype=torch.uint8, device=dev) for _ in range(R)]
+        ranges = [(o, min(budget, total - o)) for o in range(0, total, budget)]
+        bps, bus = [], []
+        for r in range(R):
+            bp, bu = mdt.Batch(), mdt.Batch()
+            for o, n in ranges:
+                bp.add_pack(srcs[r].data_ptr(), count, t, o, parts_p[r].data_ptr() + o, n)
+                bu.add_unpack(parts_p[r].data_ptr() + o, n, parts_d[r].data_ptr(), count, t, o)
+            bps.append(bp)
+            bus.append(bu)
+        log(f"chunked {name}: autotune")
+        cp = mdt.autotune_set(bps, ms)
+        cu = mdt.autotune_set(bus, ms)
+        for bp in bps:
+            bp.set_config(cp)
+        for bu in bus:
+            bu.set_config(cu)
+        it = {"p": 0, "u": 0}
+
+        def nxt(k):
+            it[k] += 1
+            return it[k] % R
+
+        def whole_pack():
+            mdt.mdt_pack_enqueue(srcs[nxt("p")].data_ptr(), count, t, 0, whole_p.data_ptr(), -1, ms)
+
+        def whole_unpack():
+            mdt.mdt_unpack_enqueue(whole_p.data_ptr(), total, whole_d.data_ptr(), count, t, 0, ms)
+
+        def batch_pack():
+            bps[nxt("p")].launch(ms)
+
+        def batch_unpack():
+            bus[nxt("u")].launch(ms)
+
+        def plain_pack():
+            r = nxt("p")
+            for o, n in ranges:
+                mdt.mdt_pack_enqueue(srcs[r].data_ptr(), count, t, o, parts_p[r].data_ptr() + o, n, ms)
+
+        def plain_unpack():
+            r = nxt("u")
+            for o, n in ranges:
+                mdt.mdt_unpack_enqueue(parts_p[r].data_ptr() + o, n, parts_d[r].data_ptr(), count, t, o, ms)
+
+        res = {"workload": W["desc"], "packed_bytes": total, "ranges": len(ranges),
+               "last_range_bytes": ranges[-1][1], "autotuned": {"pack": mdt.config_dict(cp),
+                                                               "unpack": mdt.config_dict(cu)}}
+        for form, fp, fu, launches in (("whole", whole_pack, whole_unpack, 1),
+                                       ("batched_ranges", batch_pack, batch_unpack, 1),
+                                       ("plain_ranges", plain_pack, plain_unpack, len(ranges))):
+            log(f"chunked {name}: {form}")
+            wp, dp = time_region(torch, stream, fp, reps, R)
+            wu, du = time_region(torch, stream, fu, reps, R)
+            res[form] = {"launches_per_direction": launches,
+                         "pack_us": round(wp * 1e6, 2), "unpack_us": round(wu * 1e6, 2),
+                         "pack_device_us": round(dp * 1e6, 2), "unpack_device_us": round(du * 1e6, 2),
+                         "GBps": round(4 * total / (wp + wu) / 1e9, 2)}
+        # equality of the range forms with the whole transfer (every copy ran)
+        torch.cuda.synchronize()
+        res["ranges_equal_whole"] = (all(bool(torch.equal(p, whole_p)) for p in parts_p) and
+                                     all(bool(torch.equal(d, whole_d)) for d in parts_d))
+        out[name] = res
+        del srcs, whole_p, parts_p, whole_d, parts_d, bps, bus
+        torch.cuda.empty_cache()
     return out
 
 
@@ -840,10 +938,16 @@ def standalone(block, args, name):
     if name == "serve":
         head.update(value=block["served"]["GBps"], ms_per_step=round(block["served"]["elapsed_s"] * 1e3, 3),
                     steps=1, warmup=0)
+        head["config"] = {"workload": block["workload"]}
+    elif name == "chunked":
+        b = block["particles"]["batched_ranges"]
+        head.update(value=b["GBps"], ms_per_step=round((b["pack_us"] + b["unpack_us"]) * 1e-3, 4))
+        head["config"] = {"workload": "1 MiB byte ranges of the particle records, packed then unpacked as one "
+                                      "batch per direction"}
     else:
         head.update(value=block["batched"]["GBps"], ms_per_step=block["batched"]["makespan_ms"],
                     roofline=block["roofline"])
-    head["config"] = {"workload": block["workload"]}
+        head["config"] = {"workload": block["workload"]}
     head[name] = block
     print(json.dumps(head), flush=True)
     return 0
@@ -870,6 +974,8 @@ def main():
                           "batch4096")
     if args.workload == "copy":
         return copy_bench(args, torch, mdt)
+    if args.workload == "chunked":
+        return standalone(chunked_block(args, torch, mdt), args, "chunked")
     W = workload(args.workload)
     stream = torch.cuda.current_stream()
     ms = mdt.Stream(stream.cuda_stream)
@@ -962,6 +1068,9 @@ def main():
     if args.workload == "halo" and not args.no_extras:
         log("batch4096 block")
         out["batch4096"] = batch4096_block(args, torch, mdt)
+        torch.cuda.empty_cache()
+        log("chunked block")
+        out["chunked_1MiB"] = chunked_block(args, torch, mdt)
         torch.cuda.empty_cache()
         log("serve block")
         out["serve"] = serve_block(args, torch, mdt)

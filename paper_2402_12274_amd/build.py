@@ -13,8 +13,12 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmdt.so")
 LOADGEN = os.path.join(HERE, "libmdt_loadgen.so")
 
-SOURCES = ["types.cpp", "compile.cpp", "api.cpp", "requests.cpp", "device.hip", "batch.hip", "batch_p0u0.hip", "batch_p0u1.hip",
-           "batch_p1u0.hip", "batch_p1u1.hip", "batch_p2u0.hip", "batch_p2u1.hip", "server.cpp"]
+# (source, extra defines): the batch kernel variants compile once per launch
+# policy and direction
+SOURCES = [(s, ()) for s in ("types.cpp", "compile.cpp", "api.cpp", "requests.cpp", "device.hip", "batch.hip",
+                             "server.cpp")]
+SOURCES += [("batch_variants.hip", (f"MDT_BATCH_POLICY={p}", f"MDT_BATCH_UNPACK={u}")) for p in (0, 1, 2)
+            for u in (0, 1)]
 ARCH = os.environ.get("MDT_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall", "-Wno-unused-function",
@@ -22,10 +26,12 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall", "-Wno-un
 HIP_ONLY = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def _compile(src: str) -> str:
+def _compile(item) -> str:
+    src, defines = item if isinstance(item, tuple) else (item, ())
     path = os.path.join(CSRC, src)
-    obj = os.path.join(BUILD, src.replace(".", "_") + ".o")
-    cmd = ["hipcc", *COMMON]
+    tag = "".join("_" + d.split("=")[1] for d in defines)
+    obj = os.path.join(BUILD, src.replace(".", "_") + tag + ".o")
+    cmd = ["hipcc", *COMMON, *[f"-D{d}" for d in defines]]
     if src.endswith(".hip"):
         cmd += HIP_ONLY
     cmd += ["-c", path, "-o", obj]
@@ -37,7 +43,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s[0]))]
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"

@@ -222,7 +222,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchHeader *__restric
 namespace mdt {
 
 // Launch one direction's kernel, compiled for the tile bodies `body` names
-// (a set of BODY_* bits).  Defined in batch_p<POLICY>u<UNPACK>.hip.
+// (a set of BODY_* bits).  Defined in batch_variants.hip, compiled once per pair.
 template <int POLICY, int UNPACK>
 void launch_batch_dir(dim3 grid, size_t lds, hipStream_t s, const BatchHeader *H, const ReqDesc *R,
                       const int64_t *tile0, const int32_t *order, unsigned long long *counter, int body);
