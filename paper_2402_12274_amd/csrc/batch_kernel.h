@@ -1,6 +1,6 @@
 // batch_kernel.h -- the batch kernel: descriptors, tile bodies, and the
-// launch of one direction.  Its variants are compiled in four translation
-// units (static or dynamic split x pack or unpack direction) so they build
+// launch of one direction.  Its variants are compiled in six translation
+// units (launch policy x direction, batch_variants.hip) so they build
 // in parallel; batch.hip holds the host side.
 #pragma once
 
