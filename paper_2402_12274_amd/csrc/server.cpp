@@ -106,12 +106,28 @@ const bool DIRECT = [] {
     const char *e = getenv("MDT_SERVER_DIRECT");
     return !(e && *e == '0');
 }();
+// While launches are in flight and nothing waits to be launched, the
+// progress thread polls its counters at this interval rather than back to
+// back: every poll reads cache lines the submitting and testing clients
+// write, and a tight loop makes each of their writes a coherence miss.
+const double POLL_US = [] {
+    const char *e = getenv("MDT_SERVER_POLL_US");
+    double v = e && *e ? atof(e) : 2.0;
+    return v >= 0 && v <= 1000 ? v : 2.0;
+}();
+// A client's test records its time (for the progress thread's quiet test)
+// only when the recorded time is at least this old, so a client polling its
+// requests does not write that line on every poll.
+constexpr double CLIENT_MARK_US = 10.0;
 
 double now_us()
 {
     using namespace std::chrono;
     return (double)duration_cast<nanoseconds>(steady_clock::now().time_since_epoch()).count() * 1e-3;
 }
+
+// one spin-wait hint (the x86 PAUSE instruction)
+inline void cpu_relax() { __builtin_ia32_pause(); }
 
 struct Item {
     int unpack = 0;
@@ -235,13 +251,17 @@ struct mdt_server_s {
     std::deque<Item *> admitted;
     int64_t inflight = 0, peak_inflight = 0;
     int inject_fail = 0;
-    std::atomic<bool> run_thread{false};
     bool draining = false;       // shutdown: admit regardless of the budget
+    int64_t direct = 0;          // requests launched by their own submit (direct path)
+    // What the progress thread polls, on cache lines of their own: the
+    // counters every launch and completion update, and the two timestamps
+    // (written by reaps and by testing clients) apart from them.
+    alignas(64) std::atomic<bool> run_thread{false};
     std::atomic<int64_t> work{0};   // queued + admitted items + launches in flight
     std::atomic<int> launches_inflight{0};
-    std::atomic<double> last_reap{0.0};  // time of the last completion query round
-    std::atomic<double> last_client_test{0.0};  // time of the last client test of a launched request
-    int64_t direct = 0;          // requests launched by their own submit (direct path)
+    alignas(64) std::atomic<double> last_reap{0.0};  // time of the last completion query round
+    alignas(64) std::atomic<double> last_client_test{0.0};  // time of the last client test of a launched request
+    alignas(64) char pad_end_[1] = {};
     std::condition_variable wake;  // submit -> idle progress thread
     std::thread th;
     // stats
@@ -608,6 +628,11 @@ void thread_main(mdt_server s)
                 t - s->last_client_test.load(std::memory_order_relaxed) >= CLIENT_QUIET_US && reap_unlocked(s)) {
                 std::lock_guard<std::mutex> g(s->mu);
                 progress_locked(s);
+            } else {
+                // nothing to launch: wait out the poll interval, ending early
+                // when a submit queues work
+                while (now_us() - t < POLL_US && s->work.load(std::memory_order_relaxed) <= nl)
+                    for (int k = 0; k < 16; k++) cpu_relax();
             }
             last_active = t;
             continue;
@@ -879,7 +904,11 @@ MDT_API int mdt_server_request_test(mdt_server srv, mdt_request req, int *flag)
     Item *it = item_of(req);
     if (!valid_server(srv) || !it || !flag) return MDT_ERR_ARG;
     const int st = it->state.load(std::memory_order_acquire);
-    if (st == 2) srv->last_client_test.store(now_us(), std::memory_order_relaxed);
+    if (st == 2) {
+        const double t = now_us();
+        if (t - srv->last_client_test.load(std::memory_order_relaxed) >= CLIENT_MARK_US)
+            srv->last_client_test.store(t, std::memory_order_relaxed);
+    }
     if (st == 2 && srv->run_thread.load()) {
         // the client queries the event of its own launch only (as the caller
         // of a plain enqueue queries its own event); once it has finished,
