@@ -26,11 +26,22 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall", "-Wno-un
 HIP_ONLY = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
+def _newest_header() -> float:
+    heads = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    heads += [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
+    return max(os.path.getmtime(h) for h in heads)
+
+
 def _compile(item) -> str:
     src, defines = item if isinstance(item, tuple) else (item, ())
     path = os.path.join(CSRC, src)
     tag = "".join("_" + d.split("=")[1] for d in defines)
     obj = os.path.join(BUILD, src.replace(".", "_") + tag + ".o")
+    # MDT_BUILD_INCREMENTAL=1 (development): keep an object newer than its
+    # source and every header; the default rebuilds everything
+    if os.environ.get("MDT_BUILD_INCREMENTAL") == "1" and os.path.exists(obj) and \
+            os.path.getmtime(obj) > max(os.path.getmtime(path), _newest_header()):
+        return obj
     cmd = ["hipcc", *COMMON, *[f"-D{d}" for d in defines]]
     if src.endswith(".hip"):
         cmd += HIP_ONLY
