@@ -24,10 +24,12 @@
 #include <cstdio>
 #include <cstdlib>
 #include <mutex>
-#include <string>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
+
+#include <unistd.h>
 
 #include "core.h"
 #include "device.h"
@@ -808,14 +810,16 @@ void cache_store(const char *path, const std::string &key, const mdt_batch_confi
     std::snprintf(buf, sizeof buf, "  \"%s\": [%d, %d, %d, %d, %d]", key.c_str(), c.tile_chunks, c.wgs_per_cu,
                   c.policy, c.use_graph, c.order);
     keep.push_back(buf);
-    const std::string tmp = std::string(path) + ".tmp";
+    // a temporary of this process's own, replacing the file in one step: two
+    // processes storing at once each leave a whole file (the later one wins)
+    const std::string tmp = std::string(path) + ".tmp." + std::to_string((long long)getpid());
     FILE *f = std::fopen(tmp.c_str(), "w");
     if (!f) return;
     std::fputs("{\n", f);
     for (size_t i = 0; i < keep.size(); i++) std::fprintf(f, "%s%s\n", keep[i].c_str(), i + 1 < keep.size() ? "," : "");
     std::fputs("}\n", f);
     std::fclose(f);
-    std::rename(tmp.c_str(), path);  // replaces the file in one step
+    std::rename(tmp.c_str(), path);
 }
 
 int autotune_set(int n, mdt_batch *bs, hipStream_t s, mdt_batch_config *best)
