@@ -203,7 +203,7 @@ struct DevLayout {
     int64_t gsize;          // packed bytes of the whole group list
     int64_t gruns;          // runs of the whole group list
     int64_t nruns;          // runs of one element
-    int64_t gdisp0;         // displacement of group 0 (KIND_CONTIG / KIND_SINGLE)
+    int64_t gdisp0;         // KIND_SINGLE: displacement of group 0; KIND_CONTIG: address of the run (its leaf offset included)
     int32_t nshapes;
     int32_t dir_shift;      // directory granularity = 1 << dir_shift packed bytes
     int32_t runs_only;      // every group is a single run (varlen shape), no outer loops
@@ -397,7 +397,13 @@ MDT_HD RunInfo run_at(const DevLayout &L, uint64_t k)
     int64_t addr = 0;
     const DevShape *S;
     int64_t glen;
-    if (L.kind == KIND_CONTIG || L.kind == KIND_SINGLE) {
+    if (L.kind == KIND_CONTIG) {
+        // one run per element; gdisp0 already includes the run's offset
+        r.addr = L.gdisp0;
+        r.len = L.size;
+        return r;
+    }
+    if (L.kind == KIND_SINGLE) {
         S = &L.shape0;
         addr = L.gdisp0;
         glen = L.size;

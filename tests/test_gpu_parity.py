@@ -42,7 +42,12 @@ def _pack_dev(mdt, t, src_dev, origin, count, off, mx, out_shift=0):
     return h[out_shift:out_shift + n]
 
 
-SPECS = tiny_specs(99, 120)
+SPECS = tiny_specs(99, 120) + [
+    # one run at a nonzero offset inside the element, alone and repeated
+    ("hindexed", [1, 1], [-19, -15], ("basic", "INT32")),
+    ("contiguous", 2, ("hindexed", [1, 1], [-19, -15], ("basic", "INT32"))),
+    ("contiguous", 3, ("hindexed", [1, 1, 1], [5, 9, 13], ("basic", "INT32"))),
+]
 
 
 @pytest.mark.parametrize("i", range(len(SPECS)))
@@ -265,6 +270,10 @@ def test_device_flatten_matches_oracle(mdt):
     lens, disps = inputs.hindexed_blocks(nblocks=5000, span=1 << 20, seed=11)
     specs.append(inputs.hindexed_type(lens, disps))
     specs += tiny_specs(5, 30)
+    # one run at a nonzero offset, alone and repeated (regression)
+    I32 = ("basic", "INT32")
+    specs += [("hindexed", [1, 1], [-19, -15], I32), ("contiguous", 2, ("hindexed", [1, 1], [-19, -15], I32)),
+              ("contiguous", 3, ("hindexed", [1, 1, 1], [5, 9, 13], I32))]
     s = mdt.Stream(0)
     for spec in specs:
         note(f"flatten {str(spec)[:80]}")

@@ -53,6 +53,35 @@ def test_random_types_match_oracle(i):
     _cmp_segments(t, o)
 
 
+# Types whose element is one run that does not start at displacement 0:
+# touching blocks collapse into a single run at their first block's offset
+# (a layout that moves as one contiguous copy), alone and repeated.
+I32 = ("basic", "INT32")
+ONE_RUN_AT_OFFSET = [
+    ("hindexed", [1, 1], [-19, -15], I32),
+    ("contiguous", 2, ("hindexed", [1, 1], [-19, -15], I32)),
+    ("hvector", 1, 2, 38, ("hindexed", [1, 1], [-19, -15], I32)),
+    ("contiguous", 3, ("hindexed", [1, 1, 1], [5, 9, 13], I32)),
+    ("contiguous", 2, ("struct", [1, 1], [16, 24], [inputs.DOUBLE, inputs.DOUBLE])),
+    ("contiguous", 2, ("indexed", [2, 1], [3, 5], I32)),
+]
+
+
+@pytest.mark.parametrize("spec", ONE_RUN_AT_OFFSET)
+def test_one_run_at_an_offset_matches_oracle(spec):
+    # regression: the segment of such a type came out at twice its offset
+    t = mdt.build_type(spec)
+    o = obuild(spec)
+    _cmp_attrs(t, o)
+    _cmp_segments(t, o)
+    for count in (0, 2, 3):
+        n = o.iov_len(-1, count)[0]
+        assert t.iov_len(-1, count) == o.iov_len(-1, count)
+        b1, l1 = t.iov(0, n + 1, count)
+        b2, l2 = o.iov(0, n + 1, count)
+        assert np.array_equal(b1, b2) and np.array_equal(l1, l2), count
+
+
 def test_workload_types_match_oracle():
     specs = [inputs.vector_small(), inputs.particle_struct()]
     specs += [s for _, s in inputs.halo_faces(512)]
