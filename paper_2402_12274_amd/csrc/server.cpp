@@ -252,6 +252,7 @@ struct mdt_server_s {
     int64_t inflight = 0, peak_inflight = 0;
     int inject_fail = 0;
     bool draining = false;       // shutdown: admit regardless of the budget
+    int next_stream = 0;         // where the next stream choice starts looking
     int64_t direct = 0;          // requests launched by their own submit (direct path)
     // What the progress thread polls, on cache lines of their own: the
     // counters every launch and completion update, and the two timestamps
@@ -381,31 +382,30 @@ bool reap_unlocked(mdt_server s)
     return true;
 }
 
-// The stream a launch goes to: one with a free slot whose hardware queue
-// has the least work queued ahead of it (streams are spread over the
-// process's hardware queues in creation order, so streams i and i + k*HWQ
-// share one, and its work runs in order).  Large requests take hardware
-// queue 0 in arrival order (two large requests then finish one after the
-// other instead of both late); the others use the remaining queues.
+// The stream a launch goes to: one with a free slot and the fewest bytes in
+// flight, ties going round the streams, so that under light load successive
+// launches spread over them (the runtime spreads a process's streams over its
+// hardware queues, in a pattern of its own choosing: streams that share a
+// queue run their work in order).  Large requests take streams 0, Q, 2Q, ...
+// (Q = the hardware queue count) in arrival order; the others use the rest.
 // Caller holds s->mu.  NULL when no suitable slot is free.
 StreamState *pick_stream(mdt_server s, bool large)
 {
     const int nst = (int)s->streams.size();
-    const int hwq = std::max(1, std::min(nst, HW_QUEUES));
-    int64_t qbytes[64] = {0};
-    for (int i = 0; i < nst; i++) qbytes[i % hwq] += s->streams[(size_t)i].bytes;
+    const int part = std::max(1, std::min(nst, HW_QUEUES));
     StreamState *best = nullptr;
     int64_t best_load = 0;
-    for (int i = 0; i < nst; i++) {
+    for (int k = 0; k < nst; k++) {
+        const int i = (s->next_stream + k) % nst;
         StreamState &st = s->streams[(size_t)i];
         if (st.busy >= (int)st.slots.size()) continue;
-        if (hwq > 1 && (i % hwq == 0) != large) continue;
-        const int64_t load = qbytes[i % hwq];
-        if (!best || load < best_load || (load == best_load && st.busy < best->busy)) {
+        if (part > 1 && (i % part == 0) != large) continue;
+        if (!best || st.bytes < best_load || (st.bytes == best_load && st.busy < best->busy)) {
             best = &st;
-            best_load = load;
+            best_load = st.bytes;
         }
     }
+    if (best) s->next_stream = (int)(best - s->streams.data() + 1) % nst;
     return best;
 }
 
