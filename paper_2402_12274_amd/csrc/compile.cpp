@@ -141,7 +141,11 @@ void normalize(Shape &S)
             if ((size_t)lp.cnt * S.leaf.size() <= UNROLL_MAX) {
                 std::vector<Run> nl;
                 for (int64_t i = 0; i < lp.cnt; i++)
-                    for (const Run &r : S.leaf) nl.push_back({r.off + i * lp.stride, r.len});
+                    for (const Run &r : S.leaf) {
+                        int64_t v, o;
+                        if (!mul_ok(i, lp.stride, &v) || !add_ok(r.off, v, &o)) throw CompileError{MDT_ERR_ARG};
+                        nl.push_back({o, r.len});
+                    }
                 merge_leaf(nl);
                 S.leaf.swap(nl);
                 S.loops.pop_back();
@@ -331,6 +335,10 @@ LayoutP child_layout(TypeNode *c) { return compile_node(c); }
 
 LayoutP build(TypeNode *t)
 {
+    // a type with no data has the empty layout, whatever its parts: their
+    // displacements need not even be representable (e.g. copies of a huge
+    // extent inside a zero-count vector)
+    if (t->size == 0) return empty_layout();
     switch (t->kind) {
     case K_BASIC: {
         auto R = std::make_shared<Layout>();
@@ -751,7 +759,8 @@ void lower_records(const Layout &L, Compiled &C)
         X = D.extent;
     } else if (S.loops.size() == 1) {
         X = S.loops[0].stride;
-        count1 = D.extent != S.loops[0].cnt * S.loops[0].stride;
+        int64_t span;
+        count1 = !mul_ok(S.loops[0].cnt, S.loops[0].stride, &span) || D.extent != span;
     } else {
         return;
     }
@@ -1190,6 +1199,12 @@ int check_unpack_overlap(Compiled *c, int64_t count)
 {
     std::lock_guard<std::mutex> g(c->ov_mu);
     if (count <= c->ov_checked_count) return MDT_SUCCESS;
+    if (c->nruns == 0) return MDT_SUCCESS;  // no bytes, nothing to overlap (and no loop over count)
+    // every element's address must be representable (callers check this too)
+    int64_t span, lo, hi;
+    if (count > 1 && (__builtin_mul_overflow(count - 1, c->extent, &span) ||
+                      __builtin_add_overflow(span, c->true_lb, &lo) || __builtin_add_overflow(span, c->true_ub, &hi)))
+        return MDT_ERR_COUNT;
     int64_t te = c->true_ub - c->true_lb;
     int64_t ae = c->extent < 0 ? -c->extent : c->extent;
     if (c->self_disjoint && (count <= 1 || ae >= te)) {

@@ -11,7 +11,11 @@
 // budgets.  Envelope/contents, layout info and the error paths run too, and
 // the oracle packs and unpacks every type at random offsets and budgets.
 // Any out-of-bounds access, leak or undefined behaviour ends the run with
-// the sanitizer's report.  Prints "host sanitize ok".
+// the sanitizer's report.  Then 2000 types with huge counts, strides,
+// displacements and bounds (library only) must build or fail with
+// MDT_ERR_ARG, and commit and every query must return a result or an error,
+// with no undefined behaviour.  Prints "host sanitize ok".
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -19,6 +23,7 @@
 #include <random>
 #include <vector>
 
+#include "core.h"  // the layout compiler's own entry points (overlap check)
 #include "mdt.h"
 
 extern "C" {
@@ -320,6 +325,131 @@ void check_pair(const Pair &p)
         const int ru = orc_unpack(full.data(), total, borigin, count, p.o, 0, &got2);
         g_packs++;
         CHECK(ru == ORC_OK || ru == ORC_ERR_OVERLAP);
+        // the library's unpack overlap verdict is the oracle's
+        mdt::TypeNode *tn = reinterpret_cast<mdt::TypeNode *>(p.m);
+        const int rl = mdt::check_unpack_overlap(tn->comp.get(), count);
+        CHECK((rl == MDT_ERR_OVERLAP) == (ru == ORC_ERR_OVERLAP) && (rl == MDT_SUCCESS || rl == MDT_ERR_OVERLAP));
+    }
+}
+
+// ---- extreme parameters (library only: the oracle enumerates copies one by
+// one and is not meant for 2^40-element types) ------------------------------
+
+int64_t big_count()
+{
+    static const int64_t v[] = {0, 1, 2, 3, 1000, 1000000, (int64_t)1 << 31, (int64_t)1 << 40, (int64_t)1 << 62};
+    return v[rnd(0, 8)];
+}
+
+int64_t big_signed()
+{
+    static const int64_t v[] = {1, 7, (int64_t)1 << 20, (int64_t)1 << 40, (int64_t)1 << 61, INT64_MAX / 3};
+    const int64_t x = v[rnd(0, 5)];
+    return rnd(0, 1) ? x : -x;
+}
+
+int64_t cnt_or_big(int64_t lo, int64_t hi) { return rnd(0, 2) == 0 ? big_count() : rnd(lo, hi); }
+int64_t off_or_big(int64_t lo, int64_t hi) { return rnd(0, 2) == 0 ? big_signed() : rnd(lo, hi); }
+
+// A random type whose counts, strides, displacements, sizes and bounds are
+// often huge; every constructor must either build it or return an error
+// (MDT_ERR_ARG on overflow), with no undefined behaviour on the way.
+mdt_type gen_extreme(int depth)
+{
+    static const int codes[] = {MDT_CODE_BYTE, MDT_CODE_INT16, MDT_CODE_INT32, MDT_CODE_DOUBLE};
+    if (depth == 0 || rnd(0, 4) == 0) return mdt_basic(codes[rnd(0, 3)]);
+    const int k = (int)rnd(0, 9);
+    mdt_type c = gen_extreme(depth - 1), t = nullptr;
+    int rc = MDT_SUCCESS;
+    int64_t bl[3], d[3];
+    for (int i = 0; i < 3; i++) {
+        bl[i] = cnt_or_big(0, 3);
+        d[i] = off_or_big(-50, 60);
+    }
+    switch (k) {
+    case 0: rc = mdt_type_contiguous(cnt_or_big(0, 4), c, &t); break;
+    case 1: rc = mdt_type_vector(cnt_or_big(0, 4), cnt_or_big(0, 3), off_or_big(-4, 5), c, &t); break;
+    case 2: rc = mdt_type_create_hvector(cnt_or_big(0, 4), cnt_or_big(0, 3), off_or_big(-40, 40), c, &t); break;
+    case 3: rc = mdt_type_indexed(3, bl, d, c, &t); break;
+    case 4: rc = mdt_type_create_hindexed(3, bl, d, c, &t); break;
+    case 5: rc = mdt_type_create_hindexed_block(3, cnt_or_big(0, 3), d, c, &t); break;
+    case 6: {
+        mdt_type kids[3] = {c, gen_extreme(depth - 1), mdt_basic(codes[rnd(0, 3)])};
+        rc = mdt_type_create_struct(3, bl, d, kids, &t);
+        mdt_count a, b, n;
+        int comb = -1;
+        if (mdt_type_get_envelope(kids[1], &a, &b, &n, &comb) == MDT_SUCCESS && comb != MDT_COMBINER_NAMED)
+            mdt_type_free(&kids[1]);
+        break;
+    }
+    case 7: {
+        const int nd = (int)rnd(1, 3);
+        mdt_count sz[3], sub[3], st[3];
+        for (int i = 0; i < nd; i++) {
+            sz[i] = rnd(0, 1) ? ((int64_t)1 << rnd(10, 40)) : rnd(1, 4);
+            sub[i] = rnd(0, 1) ? sz[i] : rnd(0, std::min<int64_t>(sz[i], 4));
+            st[i] = rnd(0, std::min<int64_t>(sz[i] - sub[i], 3));
+        }
+        rc = mdt_type_create_subarray(nd, sz, sub, st, rnd(0, 1) ? MDT_ORDER_FORTRAN : MDT_ORDER_C, c, &t);
+        break;
+    }
+    case 8: rc = mdt_type_create_resized(c, off_or_big(-16, 16), rnd(0, 1) ? big_count() : rnd(1, 64), &t); break;
+    default: rc = mdt_type_dup(c, &t); break;
+    }
+    mdt_count a, b, n;
+    int comb = -1;
+    if (mdt_type_get_envelope(c, &a, &b, &n, &comb) == MDT_SUCCESS && comb != MDT_COMBINER_NAMED) mdt_type_free(&c);
+    CHECK(rc == MDT_SUCCESS || rc == MDT_ERR_ARG);
+    CHECK((rc == MDT_SUCCESS) == (t != nullptr));
+    return rc == MDT_SUCCESS ? t : mdt_basic(codes[rnd(0, 3)]);
+}
+
+int64_t g_extreme_built = 0, g_extreme_committed = 0;
+
+// Everything a caller can ask of such a type, on the host.
+void check_extreme(mdt_type t)
+{
+    mdt_count size = -1, ni, na, nt;
+    mdt_aint lb, ext, tlb, text;
+    int comb = -1;
+    CHECK(mdt_type_size(t, &size) == MDT_SUCCESS && size >= 0);
+    CHECK(mdt_type_get_extent(t, &lb, &ext) == MDT_SUCCESS);
+    CHECK(mdt_type_get_true_extent(t, &tlb, &text) == MDT_SUCCESS && text >= 0);
+    CHECK(mdt_type_get_envelope(t, &ni, &na, &nt, &comb) == MDT_SUCCESS);
+    if (comb == MDT_COMBINER_NAMED) return;
+    g_extreme_built++;
+    mdt_type c = t;
+    const int rc = mdt_type_commit(&c);
+    CHECK(rc == MDT_SUCCESS || rc == MDT_ERR_NO_MEM || rc == MDT_ERR_ARG || rc == MDT_ERR_COUNT);
+    if (rc != MDT_SUCCESS) return;
+    g_extreme_committed++;
+    mdt_layout_info li{};
+    CHECK(mdt_type_layout_info(t, &li) == MDT_SUCCESS);
+    for (mdt_count budget : {(mdt_count)-1, (mdt_count)0, (mdt_count)1, (mdt_count)4096, size / 2, size}) {
+        mdt_count k = -1, bytes = -1;
+        const int r = mdt_type_iov_len(t, budget, &k, &bytes);
+        CHECK(r == MDT_SUCCESS || r == MDT_ERR_NO_MEM || r == MDT_ERR_COUNT);
+        if (r == MDT_SUCCESS) CHECK(k >= 0 && bytes >= 0 && bytes <= size);
+    }
+    mdt::TypeNode *tn = reinterpret_cast<mdt::TypeNode *>(t);
+    // the exact overlap check sorts every run: keep to types of few runs here
+    for (int64_t count : {(int64_t)1, (int64_t)2, (int64_t)1 << 40, (int64_t)1 << 62}) {
+        if (li.runs > 65536) break;
+        const int ro = mdt::check_unpack_overlap(tn->comp.get(), count);
+        CHECK(ro == MDT_SUCCESS || ro == MDT_ERR_OVERLAP || ro == MDT_ERR_NO_MEM || ro == MDT_ERR_COUNT);
+    }
+    mdt_iov iov[4];
+    mdt_count got = -1;
+    int r = mdt_type_iov(t, 0, iov, 4, &got);
+    CHECK(r == MDT_SUCCESS || r == MDT_ERR_NO_MEM || r == MDT_ERR_COUNT);
+    r = mdt_type_iov(t, (mdt_count)1 << 40, iov, 4, &got);
+    CHECK(r == MDT_SUCCESS || r == MDT_ERR_NO_MEM || r == MDT_ERR_COUNT);
+    for (mdt_count count : {(mdt_count)2, (mdt_count)1 << 20, (mdt_count)1 << 62}) {
+        mdt_count k = -1, bytes = -1;
+        r = mdt_type_iov_len_count(t, count, 4096, &k, &bytes);
+        CHECK(r == MDT_SUCCESS || r == MDT_ERR_NO_MEM || r == MDT_ERR_COUNT);
+        r = mdt_type_iov_count(t, count, 3, iov, 4, &got);
+        CHECK(r == MDT_SUCCESS || r == MDT_ERR_NO_MEM || r == MDT_ERR_COUNT);
     }
 }
 
@@ -350,8 +480,18 @@ int main()
         check_pair(p);
         release(p);
     }
-    std::printf("%lld derived types, %lld segments compared, %lld oracle pack/unpack rounds\n",
-                (long long)g_derived, (long long)g_segments, (long long)g_packs);
+    for (g_case = 0; g_case < 2000; g_case++) {
+        mdt_type t = gen_extreme((int)rnd(1, 3));
+        check_extreme(t);
+        mdt_count a, b, n;
+        int comb = -1;
+        if (mdt_type_get_envelope(t, &a, &b, &n, &comb) == MDT_SUCCESS && comb != MDT_COMBINER_NAMED)
+            CHECK(mdt_type_free(&t) == MDT_SUCCESS);
+    }
+    std::printf("%lld derived types, %lld segments compared, %lld oracle pack/unpack rounds; "
+                "%lld extreme types built, %lld committed\n",
+                (long long)g_derived, (long long)g_segments, (long long)g_packs, (long long)g_extreme_built,
+                (long long)g_extreme_committed);
     std::printf("host sanitize ok\n");
     return 0;
 }
