@@ -466,6 +466,17 @@ void check_errors()
     CHECK(mdt_type_free(&t) == MDT_SUCCESS && t == nullptr);
     CHECK(mdt_type_free(&t) != MDT_SUCCESS);
     CHECK(mdt_type_iov_len_count(D, -1, -1, nullptr, nullptr) != MDT_SUCCESS);
+    // regressions: a zero-count vector of copies of a 2^62 extent commits
+    // (its parts are never laid out), and the overlap check of a type with
+    // no bytes returns at once for 2^40 elements
+    mdt_type big = nullptr, empty = nullptr, e2 = nullptr;
+    CHECK(mdt_type_create_resized(D, -((int64_t)1 << 61), (int64_t)1 << 62, &big) == MDT_SUCCESS);
+    CHECK(mdt_type_create_hvector(0, 3, 1 << 20, big, &empty) == MDT_SUCCESS);
+    CHECK(mdt_type_commit(&empty) == MDT_SUCCESS);
+    CHECK(mdt_type_create_resized(empty, 0, 8, &e2) == MDT_SUCCESS && mdt_type_commit(&e2) == MDT_SUCCESS);
+    CHECK(mdt::check_unpack_overlap(reinterpret_cast<mdt::TypeNode *>(e2)->comp.get(), (int64_t)1 << 40) ==
+          MDT_SUCCESS);
+    CHECK(mdt_type_free(&e2) == MDT_SUCCESS && mdt_type_free(&empty) == MDT_SUCCESS && mdt_type_free(&big) == MDT_SUCCESS);
     int e = 0;
     CHECK(orc_vector(-1, 1, 1, nullptr, &e) == nullptr);
 }
