@@ -4,7 +4,8 @@
 // The library's constructors and layout compiler (types.cpp, compile.cpp,
 // compiled unchanged with the host compiler; host_stub.cpp stands in for
 // the device tables) and the oracle (oracle/oracle.c) build the same
-// seeded random types side by side -- every constructor, nested, with
+// seeded random types side by side -- every constructor (distributed
+// arrays with invalid arguments among them), nested, with
 // negative strides and displacements, zero block lengths, empty subarrays,
 // resized bounds -- and must agree on the attributes, on every segment of
 // one element and of 0, 2 and 3 elements, and on iov_len at a spread of
@@ -78,7 +79,7 @@ Pair basic()
 Pair gen(int depth)
 {
     if (depth == 0 || rnd(0, 4) == 0) return basic();
-    const int k = (int)rnd(0, 10);
+    const int k = (int)rnd(0, 11);
     Pair c = k == 8 ? Pair{} : gen(depth - 1);
     Pair p;
     int e = 0, rm = MDT_SUCCESS;
@@ -167,6 +168,26 @@ Pair gen(int depth)
         const int64_t lb = rnd(-16, 16), ext = rnd(1, 64);
         rm = mdt_type_create_resized(c.m, lb, ext, &p.m);
         p.o = orc_resized(c.o, lb, ext, &e);
+        break;
+    }
+    case 11: {
+        // a distributed array: every distribution, default and explicit
+        // arguments (some of them invalid: both sides must refuse those)
+        const int nd = (int)rnd(1, 3);
+        int64_t gs[3];
+        int dist[3], darg[3], ps[3], size = 1;
+        for (int i = 0; i < nd; i++) {
+            gs[i] = rnd(1, 9);
+            dist[i] = (int)rnd(0, 2);
+            ps[i] = dist[i] == MDT_DISTRIBUTE_NONE && rnd(0, 7) ? 1 : (int)rnd(1, 3);
+            darg[i] = rnd(0, 2) == 0 ? MDT_DISTRIBUTE_DFLT_DARG : (int)rnd(0, 5);
+            size *= ps[i];
+        }
+        const int rank = (int)rnd(0, size);  // size itself: an invalid rank
+        const int order = (int)rnd(0, 1);
+        rm = mdt_type_create_darray(size, rank, nd, gs, dist, darg, ps, order ? MDT_ORDER_FORTRAN : MDT_ORDER_C, c.m,
+                                    &p.m);
+        p.o = orc_darray(size, rank, nd, gs, dist, darg, ps, order ? ORC_ORDER_FORTRAN : ORC_ORDER_C, c.o, &e);
         break;
     }
     default:
