@@ -253,6 +253,13 @@ def test_contiguous_and_degenerate(mdt):
     # an empty type
     e = mdt.build_type(("vector", 0, 1, 2, inputs.DOUBLE))
     assert _pack_dev(mdt, e, src, 0, 5, 0, -1).size == 0
+    # regressions: empty types whose parts are not representable commit, and
+    # an unpack of 2^40 elements of an empty type returns at once
+    huge = ("resized", -(1 << 61), 1 << 62, inputs.DOUBLE)
+    e2 = mdt.build_type(("hvector", 0, 3, 1 << 20, huge))
+    assert _pack_dev(mdt, e2, src, 0, 1, 0, -1).size == 0
+    e3 = mdt.build_type(("resized", 0, 8, ("vector", 0, 1, 2, inputs.DOUBLE)))
+    assert mdt.mdt_unpack(src.data_ptr(), 0, src.data_ptr(), 1 << 40, e3, 0) == 0
     # truncation is an error and writes nothing
     dst = zeros_dev(64, 0)
     with pytest.raises(mdt.MdtError) as ex:
