@@ -16,7 +16,7 @@ LOADGEN = os.path.join(HERE, "libmdt_loadgen.so")
 # (source, extra defines): the batch kernel variants compile once per launch
 # policy and direction
 SOURCES = [(s, ()) for s in ("types.cpp", "compile.cpp", "api.cpp", "requests.cpp", "device.hip", "batch.hip",
-                             "server.cpp")]
+                             "server.cpp", "trace.cpp")]
 SOURCES += [("batch_variants.hip", (f"MDT_BATCH_POLICY={p}", f"MDT_BATCH_UNPACK={u}")) for p in (0, 1, 2)
             for u in (0, 1)]
 ARCH = os.environ.get("MDT_OFFLOAD_ARCH", "gfx950")
@@ -58,7 +58,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-lpthread"]
+    cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-lpthread", "-ldl"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

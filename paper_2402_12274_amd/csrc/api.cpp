@@ -16,6 +16,7 @@
 #include "core.h"
 #include "device.h"
 #include "requests.h"
+#include "trace.h"
 
 namespace mdt {
 
@@ -210,6 +211,7 @@ extern "C" {
 MDT_API int mdt_pack(const void *inbuf, mdt_count incount, mdt_type t, mdt_count inoffset, void *outbuf,
                      mdt_count max_pack_bytes, mdt_count *actual_pack_bytes)
 {
+    mdt::TraceRange trace_("mdt_pack");
     if (!actual_pack_bytes) return MDT_ERR_ARG;
     int64_t n = 0;
     int rc = pack_common(inbuf, incount, t, inoffset, outbuf, max_pack_bytes, &n, nullptr, nullptr);
@@ -226,6 +228,7 @@ MDT_API int mdt_pack(const void *inbuf, mdt_count incount, mdt_type t, mdt_count
 MDT_API int mdt_typed_copy(const void *src, mdt_count srccount, mdt_type srctype, void *dst, mdt_count dstcount,
                            mdt_type dsttype, mdt_count offset, mdt_count max_bytes, mdt_count *actual)
 {
+    mdt::TraceRange trace_("mdt_typed_copy");
     if (!actual) return MDT_ERR_ARG;
     int64_t n = 0;
     int rc = copy_common(src, srccount, srctype, dst, dstcount, dsttype, offset, max_bytes, &n, nullptr, nullptr);
@@ -242,6 +245,7 @@ MDT_API int mdt_typed_copy(const void *src, mdt_count srccount, mdt_type srctype
 MDT_API int mdt_unpack(const void *inbuf, mdt_count insize, void *outbuf, mdt_count outcount, mdt_type t,
                        mdt_count outoffset, mdt_count *actual_unpack_bytes)
 {
+    mdt::TraceRange trace_("mdt_unpack");
     if (!actual_unpack_bytes) return MDT_ERR_ARG;
     int64_t n = 0;
     int rc = unpack_common(inbuf, insize, outbuf, outcount, t, outoffset, &n, nullptr, nullptr);
@@ -293,6 +297,7 @@ MDT_API int mdt_pack_enqueue(const void *inbuf, mdt_count incount, mdt_type t, m
                              void *outbuf, mdt_count max_pack_bytes, mdt_count *actual_pack_bytes,
                              mdt_stream s, mdt_request *req)
 {
+    mdt::TraceRange trace_("mdt_pack_enqueue");
     if (!valid_stream(s)) return MDT_ERR_ARG;
     return pack_common(inbuf, incount, t, inoffset, outbuf, max_pack_bytes, actual_pack_bytes, s->s, req, s);
 }
@@ -301,6 +306,7 @@ MDT_API int mdt_unpack_enqueue(const void *inbuf, mdt_count insize, void *outbuf
                                mdt_type t, mdt_count outoffset, mdt_count *actual_unpack_bytes,
                                mdt_stream s, mdt_request *req)
 {
+    mdt::TraceRange trace_("mdt_unpack_enqueue");
     if (!valid_stream(s)) return MDT_ERR_ARG;
     return unpack_common(inbuf, insize, outbuf, outcount, t, outoffset, actual_unpack_bytes, s->s, req, s);
 }
@@ -309,6 +315,7 @@ MDT_API int mdt_typed_copy_enqueue(const void *src, mdt_count srccount, mdt_type
                                    mdt_count dstcount, mdt_type dsttype, mdt_count offset, mdt_count max_bytes,
                                    mdt_count *actual, mdt_stream s, mdt_request *req)
 {
+    mdt::TraceRange trace_("mdt_typed_copy_enqueue");
     if (!valid_stream(s)) return MDT_ERR_ARG;
     return copy_common(src, srccount, srctype, dst, dstcount, dsttype, offset, max_bytes, actual, s->s, req, s);
 }
@@ -316,6 +323,7 @@ MDT_API int mdt_typed_copy_enqueue(const void *src, mdt_count srccount, mdt_type
 MDT_API int mdt_type_iov_enqueue(mdt_type t, mdt_count iov_offset, mdt_iov *dev_iov, mdt_count max_iov_len,
                                  const void *base, mdt_count *actual_iov_len, mdt_stream s, mdt_request *req)
 {
+    mdt::TraceRange trace_("mdt_type_iov_enqueue");
     if (!valid_stream(s) || !actual_iov_len || iov_offset < 0 || max_iov_len < 0) return MDT_ERR_ARG;
     if (max_iov_len > 0 && !dev_iov) return MDT_ERR_ARG;
     Compiled *C;
@@ -342,6 +350,7 @@ MDT_API int mdt_type_iov_count_enqueue(mdt_type t, mdt_count count, mdt_count io
                                        mdt_count max_iov_len, const void *base, mdt_count *actual_iov_len,
                                        mdt_stream s, mdt_request *req)
 {
+    mdt::TraceRange trace_("mdt_type_iov_count_enqueue");
     if (!valid_stream(s) || !actual_iov_len || count < 0 || iov_offset < 0 || max_iov_len < 0) return MDT_ERR_ARG;
     if (max_iov_len > 0 && !dev_iov) return MDT_ERR_ARG;
     Compiled *C;

@@ -35,6 +35,7 @@
 #include "device.h"
 #include "batch_kernel.h"
 #include "requests.h"
+#include "trace.h"
 
 
 using namespace mdt;
@@ -1123,6 +1124,7 @@ MDT_API int mdt_batch_get_config(mdt_batch b, mdt_batch_config *cfg)
 
 MDT_API int mdt_batch_launch(mdt_batch b, mdt_stream s, mdt_request *req)
 {
+    mdt::TraceRange trace_("mdt_batch_launch");
     if (!valid_batch(b) || !s || s->magic != STREAM_MAGIC) return MDT_ERR_ARG;
     int rc = launch(b, s->s);
     if (rc) return rc;
@@ -1131,12 +1133,14 @@ MDT_API int mdt_batch_launch(mdt_batch b, mdt_stream s, mdt_request *req)
 
 MDT_API int mdt_batch_launch_noalloc(mdt_batch b, mdt_stream s)
 {
+    mdt::TraceRange trace_("mdt_batch_launch_noalloc");
     if (!valid_batch(b) || !s || s->magic != STREAM_MAGIC) return MDT_ERR_ARG;
     return launch_noalloc(b, s->s);
 }
 
 MDT_API int mdt_batch_autotune_set(int n, mdt_batch *batches, mdt_stream s, mdt_batch_config *best)
 {
+    mdt::TraceRange trace_("mdt_batch_autotune_set");
     if (n <= 0 || !batches || !s || s->magic != STREAM_MAGIC) return MDT_ERR_ARG;
     for (int i = 0; i < n; i++)
         if (!valid_batch(batches[i])) return MDT_ERR_ARG;
@@ -1145,6 +1149,7 @@ MDT_API int mdt_batch_autotune_set(int n, mdt_batch *batches, mdt_stream s, mdt_
 
 MDT_API int mdt_batch_autotune(mdt_batch b, mdt_stream s, mdt_batch_config *best)
 {
+    mdt::TraceRange trace_("mdt_batch_autotune");
     if (!valid_batch(b) || !s || s->magic != STREAM_MAGIC) return MDT_ERR_ARG;
     return autotune_set(1, &b, s->s, best);
 }

@@ -44,6 +44,7 @@
 #include "core.h"
 #include "device.h"
 #include "requests.h"
+#include "trace.h"
 
 namespace mdt {
 int batch_launch_internal(mdt_batch b, hipStream_t s);
@@ -844,6 +845,7 @@ MDT_API int mdt_server_free(mdt_server *ps)
 MDT_API int mdt_server_submit_pack(mdt_server srv, const void *inbuf, mdt_count incount, mdt_type t,
                                    mdt_count inoffset, mdt_count max_pack_bytes, mdt_request *req)
 {
+    mdt::TraceRange trace_("mdt_server_submit_pack");
     if (!valid_server(srv) || !req || inoffset < 0 || max_pack_bytes < -1) return MDT_ERR_ARG;
     Compiled *C;
     DeviceTables *D;
@@ -871,6 +873,7 @@ MDT_API int mdt_server_submit_pack(mdt_server srv, const void *inbuf, mdt_count 
 MDT_API int mdt_server_submit_unpack(mdt_server srv, const void *inbuf, mdt_count insize, void *outbuf,
                                      mdt_count outcount, mdt_type t, mdt_count outoffset, mdt_request *req)
 {
+    mdt::TraceRange trace_("mdt_server_submit_unpack");
     if (!valid_server(srv) || !req || insize < 0 || outoffset < 0) return MDT_ERR_ARG;
     Compiled *C;
     DeviceTables *D;
@@ -991,6 +994,7 @@ MDT_API int mdt_server_request_release(mdt_server srv, mdt_request *preq)
 
 MDT_API int mdt_server_progress(mdt_server srv)
 {
+    mdt::TraceRange trace_("mdt_server_progress");
     if (!valid_server(srv)) return MDT_ERR_ARG;
     return progress(srv);
 }

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "core.h"
+#include "trace.h"
 
 namespace mdt {
 
@@ -646,6 +647,7 @@ MDT_API int mdt_type_get_contents(mdt_type t, mdt_count max_integers, mdt_count 
 
 MDT_API int mdt_type_commit(mdt_type *t)
 {
+    mdt::TraceRange trace_("mdt_type_commit");
     if (!t) return MDT_ERR_ARG;
     CHECK_TYPE(*t);
     return commit_type(as_node(*t));

@@ -80,3 +80,28 @@ def test_batch_config_validation():
             raise AssertionError(f"config {cfg} accepted")
         got = b.get_config()
         assert tuple(getattr(got, f) for f, _ in got._fields_) == good[-1]
+
+
+def test_roctx_tracing_leaves_results_alone():
+    """With MDT_ROCTX=1 the library wraps its host-side operations in roctx
+    ranges (seen by rocprofv3 --marker-trace); the results are the same as
+    without it.  (Whether the ranges reach a profiler is checked on the GPU
+    box with a marker trace; the HIP runtime maps the roctx library either
+    way, so a process's mappings cannot tell.)"""
+    import os
+    import subprocess
+    import sys
+
+    code = ("from paper_2402_12274_amd import mdt\n"
+            "t = mdt.build_type(('struct', [1, 3], [0, 8], [('basic', 'INT32'), ('basic', 'DOUBLE')]))\n"
+            "print(t.iov_len(-1), t.iov(0, 4)[0].tolist(), t.iov_len(-1, 3))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = {}
+    for flag in ("0", "1"):
+        env = dict(os.environ, MDT_ROCTX=flag, PYTHONPATH=root)
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=root,
+                           timeout=300)
+        assert r.returncode == 0, r.stderr
+        out[flag] = r.stdout.strip().splitlines()[-1]
+    # 3 records: [0,4) [8,36) [40,68) [72,96) -- a record's last run meets the next one's first
+    assert out["0"] == out["1"] == "(2, 28) [0, 8] (4, 84)", out

@@ -42,9 +42,9 @@ def test_host_code_under_address_and_ub_sanitizers():
         exe = os.path.join(td, "host_sanitize")
         cmd = ["g++", "-std=c++17", "-O1", "-g", *SAN, "-D__HIP_PLATFORM_AMD__", "-I", ROCM_INC,
                "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-I", ORACLE,
-               os.path.join(CSRC, "types.cpp"), os.path.join(CSRC, "compile.cpp"),
+               os.path.join(CSRC, "types.cpp"), os.path.join(CSRC, "compile.cpp"), os.path.join(CSRC, "trace.cpp"),
                os.path.join(NATIVE, "host_stub.cpp"), os.path.join(NATIVE, "host_sanitize.cpp"), obj,
-               "-o", exe, "-lpthread"]
+               "-o", exe, "-lpthread", "-ldl"]
         subprocess.check_call(cmd)
         env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:halt_on_error=1", UBSAN_OPTIONS="halt_on_error=1")
         r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)

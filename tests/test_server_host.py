@@ -34,8 +34,8 @@ def test_server_scheduling_under_thread_sanitizer():
             pytest.skip("no ThreadSanitizer runtime for the host compiler")
         exe = os.path.join(td, "server_tsan")
         cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=thread", "-D__HIP_PLATFORM_AMD__", "-I", ROCM_INC,
-               "-I", os.path.join(ROOT, "include"), "-I", CSRC, os.path.join(CSRC, "server.cpp"),
-               os.path.join(NATIVE, "server_stub.cpp"), os.path.join(NATIVE, "server_tsan.cpp"), "-o", exe, "-lpthread"]
+               "-I", os.path.join(ROOT, "include"), "-I", CSRC, os.path.join(CSRC, "server.cpp"), os.path.join(CSRC, "trace.cpp"),
+               os.path.join(NATIVE, "server_stub.cpp"), os.path.join(NATIVE, "server_tsan.cpp"), "-o", exe, "-lpthread", "-ldl"]
         subprocess.check_call(cmd)
         env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66")
         r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
