@@ -7,7 +7,8 @@ with the oracle.
   byte ranges, into guard-filled outputs; flattened on the device (counts
   1 and 37); unpacked into canary-filled
   buffers when the typemap does not overlap; each seed's count-37 packs run
-  as one batch in six launch configurations.
+  as one batch in six launch configurations, and their unpacks as one batch
+  in the same six and through the launch that allocates nothing.
 - Medium types (counts and block lengths in the hundreds, elements spanning
   many tiles, up to 8 MiB packed), about 10 per seed: packed whole and over
   a random range, unpacked into canaries.  And typed copies between random
@@ -92,10 +93,10 @@ def test_random_types_sweep(env, seed):
                 mdt.mdt_unpack(fin.data_ptr(), total, dst.data_ptr() + origin, count, t, 0)
                 assert first_diff(to_host(dst), dexp) is None, (spec, count, first_diff(to_host(dst), dexp))
                 if count == 37:
-                    batch_cases.append((t, src, origin, count, total, full))
+                    batch_cases.append((t, src, origin, count, total, full, dexp, size))
     outs = [zeros_dev(c[4] + 32, 0xEE) for c in batch_cases]
     b = mdt.Batch()
-    for (t, src, origin, count, total, full), out in zip(batch_cases, outs):
+    for (t, src, origin, count, total, full, _, _), out in zip(batch_cases, outs):
         b.add_pack(src.data_ptr() + origin, count, t, 0, out.data_ptr() + 5, -1)
     for cfg in CFGS:
         note(f"sweep seed {seed} batch {cfg}")
@@ -104,10 +105,30 @@ def test_random_types_sweep(env, seed):
         b.set_config(mdt.BatchConfig(*cfg))
         b.launch(ms)
         torch.cuda.synchronize()
-        for k, ((t, src, origin, count, total, full), out) in enumerate(zip(batch_cases, outs)):
+        for k, ((t, src, origin, count, total, full, _, _), out) in enumerate(zip(batch_cases, outs)):
             h = to_host(out)
             assert first_diff(h[5:5 + total], full) is None, (cfg, k, first_diff(h[5:5 + total], full))
             assert (h[:5] == 0xEE).all() and (h[5 + total:] == 0xEE).all(), (cfg, k, "wrote outside")
+    # the same requests' unpacks as one batch, into canary-filled buffers, in
+    # every configuration and through the launch that allocates nothing
+    ins = [to_dev(c[5]) for c in batch_cases]
+    dsts = [zeros_dev(c[7], 0x5A) for c in batch_cases]
+    bu = mdt.Batch()
+    for (t, src, origin, count, total, full, dexp, size), fin, d in zip(batch_cases, ins, dsts):
+        bu.add_unpack(fin.data_ptr(), total, d.data_ptr() + origin, count, t, 0)
+    for cfg in CFGS + [None]:
+        note(f"sweep seed {seed} unpack batch {cfg}")
+        for d in dsts:
+            d.fill_(0x5A)
+        if cfg is None:
+            bu.set_config(mdt.BatchConfig(1024, 0, 2, 0, 1))
+            bu.launch_noalloc(ms)
+        else:
+            bu.set_config(mdt.BatchConfig(*cfg))
+            bu.launch(ms)
+        torch.cuda.synchronize()
+        for k, (c, d) in enumerate(zip(batch_cases, dsts)):
+            assert first_diff(to_host(d), c[6]) is None, (cfg, k, first_diff(to_host(d), c[6]))
 
 
 BASICS = ["BYTE", "INT16", "INT32", "FLOAT", "DOUBLE", "INT64"]
