@@ -8,8 +8,9 @@
 // arrays with invalid arguments among them), nested, with
 // negative strides and displacements, zero block lengths, empty subarrays,
 // resized bounds -- and must agree on the attributes, on every segment of
-// one element and of 0, 2 and 3 elements, and on iov_len at a spread of
-// budgets.  Envelope/contents, layout info and the error paths run too, and
+// one element and of 0, 2 and 3 elements, on iov_len at a spread of
+// budgets, and on the address of every packed byte as the kernels' seek
+// (locate on the layout program, run on the host) finds it.  Envelope/contents, layout info and the error paths run too, and
 // the oracle packs and unpacks every type at random offsets and budgets.
 // Any out-of-bounds access, leak or undefined behaviour ends the run with
 // the sanitizer's report.  Then 2000 types with huge counts, strides,
@@ -43,7 +44,7 @@ namespace {
 
 int g_case = -1;
 std::mt19937_64 g_rng(20240219);
-int64_t g_derived = 0, g_segments = 0, g_packs = 0;
+int64_t g_derived = 0, g_segments = 0, g_packs = 0, g_located = 0;
 
 int64_t rnd(int64_t lo, int64_t hi) { return lo + (int64_t)(g_rng() % (uint64_t)(hi - lo + 1)); }
 
@@ -262,6 +263,27 @@ void check_segments(const Pair &p, int64_t count)
     }
     CHECK(sum == bytes);
     g_segments += nseg;
+    // the seek the kernels use (locate on the layout program, here on the
+    // host): every packed byte of the count-fold stream maps to the address
+    // the oracle's segments give it, inside a run that ends within them
+    if (bytes > 0 && bytes <= 65536) {
+        const mdt::DevLayout &L = reinterpret_cast<mdt::TypeNode *>(p.m)->comp->host;
+        int64_t pos = 0;
+        for (int64_t i = 0; i < nseg; i++) {
+            for (int64_t q = 0; q < ol[(size_t)i]; q++) {
+                const mdt::Loc l = mdt::locate_any(L, (uint64_t)(pos + q));
+                // (the contiguous kind reports its one run as unbounded)
+                const bool rem_ok = L.kind == mdt::KIND_CONTIG || (l.rem >= 1 && l.rem <= ol[(size_t)i] - q);
+                if (l.addr != ob[(size_t)i] + q || !rem_ok)
+                    std::fprintf(stderr, "count %lld byte %lld: located (%lld, %lld), oracle address %lld, segment end %lld\n",
+                                 (long long)count, (long long)(pos + q), (long long)l.addr, (long long)l.rem,
+                                 (long long)(ob[(size_t)i] + q), (long long)(ob[(size_t)i] + ol[(size_t)i]));
+                CHECK(l.addr == ob[(size_t)i] + q && rem_ok);
+            }
+            pos += ol[(size_t)i];
+        }
+        g_located += pos;
+    }
     // budgets: whole segments only, and their bytes
     const int64_t budgets[] = {0, 1, 7, bytes / 3, bytes / 2, bytes - 1, bytes};
     for (int64_t b : budgets) {
@@ -520,10 +542,10 @@ int main()
         if (mdt_type_get_envelope(t, &a, &b, &n, &comb) == MDT_SUCCESS && comb != MDT_COMBINER_NAMED)
             CHECK(mdt_type_free(&t) == MDT_SUCCESS);
     }
-    std::printf("%lld derived types, %lld segments compared, %lld oracle pack/unpack rounds; "
+    std::printf("%lld derived types, %lld segments compared, %lld bytes located, %lld oracle pack/unpack rounds; "
                 "%lld extreme types built, %lld committed\n",
-                (long long)g_derived, (long long)g_segments, (long long)g_packs, (long long)g_extreme_built,
-                (long long)g_extreme_committed);
+                (long long)g_derived, (long long)g_segments, (long long)g_located, (long long)g_packs,
+                (long long)g_extreme_built, (long long)g_extreme_committed);
     std::printf("host sanitize ok\n");
     return 0;
 }
