@@ -5,8 +5,9 @@
 - batches: every request of a mixed batch (vectors, halo faces, hindexed;
   sizes log-uniform) gives the bytes of the same request run alone, for both
   split policies, with and without graph capture, across graph replays with
-  eager work in between and after the descriptors change; the autotuner
-  returns a valid configuration;
+  eager work in between and after the descriptors change; a batch refilled
+  and relaunched on another stream while its last launch is still queued;
+  the autotuner returns a valid configuration;
 - serving: mixed pack/unpack requests served with continuous batching equal
   the same requests run alone; a tiny budget defers but does not fail;
   injected arena failures fail exactly those requests; shutdown drains.
@@ -155,6 +156,70 @@ def test_batch_equals_alone(env):
         torch.cuda.synchronize()
     for k in back:
         assert first_diff(to_host(back[k]), exp_back[k]) is None, k
+
+
+def test_batch_relaunch_on_another_stream(env):
+    """One batch launched on stream A behind a long copy, then refilled and
+    launched on stream B, then refilled again and launched back on A: each
+    launch writes what its own requests say.  Without the device-side wait on
+    a stream change, B's descriptor upload would land before A's delayed
+    kernel reads the descriptors and A's requests would be lost."""
+    torch, mdt = env
+    D = ("basic", "DOUBLE")
+    specs = [("vector", 4096, 2, 5, D), inputs.halo_face(96, 2, 1, "hi")]
+    types = [mdt.build_type(s) for s in specs]
+    otypes = [obuild(s) for s in specs]
+    span = max(sum(t.extent()) for t in types)
+    host = inputs.random_bytes(span, seed=91)
+    src = to_dev(host)
+    nreq = 48
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    msa, msb = mdt.Stream(sa.cuda_stream), mdt.Stream(sb.cuda_stream)
+    hold_src = torch.ones(1 << 29, dtype=torch.uint8, device="cuda")
+    hold_dst = torch.empty_like(hold_src)
+    for cfg in (mdt.BatchConfig(256, 4, 1, 0, 0), mdt.BatchConfig(4096, 0, 0, 1, 1)):
+        note(f"relaunch on another stream cfg={mdt.config_dict(cfg)}")
+        b = mdt.Batch()
+        b.set_config(cfg)
+        outs = [zeros_dev(nreq * t.size(), 0) for t in types]
+        ext0 = sum(types[0].extent())
+        back = zeros_dev(nreq * ext0, 0)
+        for i in range(nreq):
+            b.add_pack(src.data_ptr(), 1, types[0], 0, outs[0].data_ptr() + i * types[0].size(), -1)
+        b.launch(msa)  # sizes the batch's buffers, whose first allocation waits for the device
+        torch.cuda.synchronize()
+        outs[0].fill_(0)
+        torch.cuda.synchronize()
+        # launch 1 on A, queued behind about a millisecond of copies
+        with torch.cuda.stream(sa):
+            for _ in range(4):
+                hold_dst.copy_(hold_src)
+        b.launch(msa)
+        # launch 2 on B with other requests, at once from the host
+        b.clear()
+        for i in range(nreq):
+            b.add_pack(src.data_ptr(), 1, types[1], 0, outs[1].data_ptr() + i * types[1].size(), -1)
+        b.launch(msb)
+        # launch 3 back on A: unpack what launch 1 packed
+        b.clear()
+        for i in range(nreq):
+            b.add_unpack(outs[0].data_ptr() + i * types[0].size(), types[0].size(), back.data_ptr() + i * ext0, 1,
+                         types[0], 0)
+        b.launch(msa)
+        sa.synchronize()
+        sb.synchronize()
+        for k in range(2):
+            exp = otypes[k].pack(host, 0, 1)
+            got = to_host(outs[k]).reshape(nreq, -1)
+            for i in range(nreq):
+                assert first_diff(got[i], exp) is None, (k, i)
+        exp = np.zeros(ext0, dtype=np.uint8)
+        otypes[0].unpack(otypes[0].pack(host, 0, 1), exp, 0, 1)
+        got = to_host(back).reshape(nreq, ext0)
+        for i in range(nreq):
+            assert first_diff(got[i], exp) is None, ("unpack", i)
+        del b
+    del types
 
 
 def test_batch_mixed_directions(env):
