@@ -1,7 +1,8 @@
 """Stream order, requests, batched launches and the serving loop on the GPU.
 
 - enqueue semantics: an enqueued pack is visible to later work on the same
-  stream with no host synchronisation in between; requests complete;
+  stream with no host synchronisation in between, and to another stream
+  after it waits on an event recorded behind the pack; requests complete;
 - batches: every request of a mixed batch (vectors, halo faces, hindexed;
   sizes log-uniform) gives the bytes of the same request run alone, for both
   split policies, with and without graph capture, across graph replays with
@@ -60,6 +61,47 @@ def test_enqueue_stream_order(env):
     exp = np.zeros_like(host)
     o.unpack(ref, exp, 0, 1)
     assert first_diff(to_host(back), exp) is None
+
+
+def test_cross_stream_order_through_an_event(env):
+    """A pack enqueued on stream A behind about a millisecond of copies, an
+    event recorded after it, and the unpack of its output enqueued on stream B
+    after B waits on that event: the unpack sees the packed bytes.  A third
+    stream packs another layout meanwhile, untouched by either."""
+    torch, mdt = env
+    note("cross-stream order through an event")
+    spec_a = inputs.halo_face(128, 4, 2, "lo")
+    spec_c = ("vector", 1 << 16, 3, 11, inputs.DOUBLE)
+    ta, tc = mdt.build_type(spec_a), mdt.build_type(spec_c)
+    oa, oc = obuild(spec_a), obuild(spec_c)
+    host = inputs.random_bytes(128 ** 3 * 8, seed=57)
+    host_c = inputs.random_bytes(sum(tc.extent()), seed=58)
+    src, src_c = to_dev(host), to_dev(host_c)
+    packed = zeros_dev(ta.size(), 0)
+    back = zeros_dev(host.size, 0)
+    out_c = zeros_dev(tc.size(), 0)
+    hold_src = torch.ones(1 << 29, dtype=torch.uint8, device="cuda")
+    hold_dst = torch.empty_like(hold_src)
+    sa, sb, sc = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(sa):
+        for _ in range(4):
+            hold_dst.copy_(hold_src)
+    n, _ = mdt.mdt_pack_enqueue(src.data_ptr(), 1, ta, 0, packed.data_ptr(), -1, mdt.Stream(sa.cuda_stream))
+    ev = torch.cuda.Event()
+    ev.record(sa)
+    sb.wait_event(ev)
+    m, _ = mdt.mdt_unpack_enqueue(packed.data_ptr(), n, back.data_ptr(), 1, ta, 0, mdt.Stream(sb.cuda_stream))
+    k, _ = mdt.mdt_pack_enqueue(src_c.data_ptr(), 1, tc, 0, out_c.data_ptr(), -1, mdt.Stream(sc.cuda_stream))
+    assert n == m == ta.size() and k == tc.size()
+    sb.synchronize()
+    sc.synchronize()
+    ref = oa.pack(host, 0, 1)
+    exp = np.zeros_like(host)
+    oa.unpack(ref, exp, 0, 1)
+    assert first_diff(to_host(back), exp) is None
+    assert first_diff(to_host(packed), ref) is None
+    assert first_diff(to_host(out_c), oc.pack(host_c, 0, 1)) is None
 
 
 def _mix(nreq, seed, n_face=128, vec_count=1 << 14, hi=1 << 20):
