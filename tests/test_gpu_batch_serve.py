@@ -10,7 +10,8 @@
   and relaunched on another stream while its last launch is still queued;
   the autotuner returns a valid configuration;
 - serving: mixed pack/unpack requests served with continuous batching equal
-  the same requests run alone; a tiny budget defers but does not fail;
+  the same requests run alone; four client threads at once get the oracle's
+  bytes; a tiny budget defers but does not fail;
   injected arena failures fail exactly those requests; shutdown drains.
 """
 import numpy as np
@@ -405,6 +406,98 @@ def test_server_mix_equals_alone(env):
     s = srv.stats()
     assert s["completed"] == len(handles) + len(ups) and s["failed"] == 0
     assert s["p99_us"] >= s["p50_us"] > 0
+    srv.stop()
+    srv.close()
+
+
+def test_server_concurrent_clients(env):
+    """Four client threads submit to one server at once (the library's calls
+    run without the interpreter lock): two submit packs of a mix of faces,
+    vectors and hindexed ranges, two submit unpacks of face streams into
+    destinations of their own, while the progress thread runs.  Every
+    request completes with the oracle's bytes."""
+    import threading
+
+    torch, mdt = env
+    n_face, vec_count = 96, 1 << 13
+    reqs, hspec = _mix(240, 123, n_face, vec_count, hi=1 << 19)
+    hosts = {k: inputs.random_bytes(_arena_bytes(k, n_face, vec_count), seed=80 + i)
+             for i, k in enumerate(("vector", "face", "hindexed"))}
+    arenas = {k: to_dev(v) for k, v in hosts.items()}
+    types, otypes = {}, {}
+    for r in reqs:
+        if r["spec_key"] not in types:
+            spec = r["spec"] if r["spec"] is not None else hspec
+            types[r["spec_key"]] = mdt.build_type(spec)
+            otypes[r["spec_key"]] = obuild(spec)
+    faces = [(label, spec) for label, spec in inputs.halo_faces(n_face)][:6]
+    ftypes = [mdt.build_type(spec) for _, spec in faces]
+    ofaces = [obuild(spec) for _, spec in faces]
+    fpacked = [o.pack(hosts["face"], 0, 1) for o in ofaces]
+    fsrc = [to_dev(p) for p in fpacked]
+    nup = 30
+    dsts = [[zeros_dev(n_face ** 3 * 8, 0) for _ in range(nup)] for _ in range(2)]
+    torch.cuda.synchronize()
+    srv = mdt.Server(nstreams=8, budget_bytes=1 << 30, max_batch=32, max_inflight=2)
+    srv.start()
+    note("server, four client threads")
+    got = [[] for _ in range(4)]
+    errors = []
+
+    def packer(w):
+        try:
+            for i in range(w, len(reqs), 2):
+                r = reqs[i]
+                t = types[r["spec_key"]]
+                n = min(r["target"], t.size())
+                got[w].append((srv.submit_pack(arenas[r["kind"]].data_ptr(), 1, t, 0, n), i, n))
+            for h, _, _ in got[w]:
+                srv.wait(h)
+        except Exception as e:  # reported by the main thread
+            errors.append(e)
+
+    def unpacker(w):
+        try:
+            for j in range(nup):
+                k = (j + w) % len(faces)
+                h = srv.submit_unpack(fsrc[k].data_ptr(), fpacked[k].size, dsts[w - 2][j].data_ptr(), 1, ftypes[k], 0)
+                got[w].append((h, k, j))
+            for h, _, _ in got[w]:
+                srv.wait(h)
+        except Exception as e:
+            errors.append(e)
+
+    threads = [threading.Thread(target=packer, args=(w,)) for w in (0, 1)] + \
+              [threading.Thread(target=unpacker, args=(w,)) for w in (2, 3)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=60)
+        assert not th.is_alive()
+    assert not errors, errors
+    torch.cuda.synchronize()
+    for w in (0, 1):
+        for h, i, n in got[w]:
+            st, pk, nb, _ = srv.result(h)
+            assert st == 0 and nb == n, (w, i)
+            out = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+            if n:
+                hip_copy(torch, out, pk, n)
+            exp = otypes[reqs[i]["spec_key"]].pack(hosts[reqs[i]["kind"]], 0, 1, 0, n)
+            assert first_diff(to_host(out)[:n], exp) is None, (w, i)
+            srv.release(h)
+    expu = []
+    for k, o in enumerate(ofaces):
+        e = np.zeros(n_face ** 3 * 8, np.uint8)
+        o.unpack(fpacked[k], e, 0, 1)
+        expu.append(e)
+    for w in (2, 3):
+        for h, k, j in got[w]:
+            assert srv.result(h)[0] == 0
+            assert first_diff(to_host(dsts[w - 2][j]), expu[k]) is None, (w, k, j)
+            srv.release(h)
+    st = srv.stats()
+    assert st["completed"] == len(reqs) + 2 * nup and st["failed"] == 0
     srv.stop()
     srv.close()
 
