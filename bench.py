@@ -959,8 +959,8 @@ def standalone(block, args, name):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported on this build "
-              "(the single-GPU kernel is the measured unit; see the design notes on sharding)",
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library runs one GPU's "
+              "share of the work, and splitting a transfer across GPUs (by packed byte range) is not built",
               file=sys.stderr)
         return 2
     import torch
