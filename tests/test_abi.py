@@ -85,8 +85,8 @@ def test_batch_config_validation():
 def test_roctx_tracing_leaves_results_alone():
     """With MDT_ROCTX=1 the library wraps its host-side operations in roctx
     ranges (seen by rocprofv3 --marker-trace); the results are the same as
-    without it.  (Whether the ranges reach a profiler is checked on the GPU
-    box with a marker trace; the HIP runtime maps the roctx library either
+    without it.  (Whether the ranges reach a profiler is checked on a GPU
+    with a marker trace; the HIP runtime maps the roctx library either
     way, so a process's mappings cannot tell.)"""
     import os
     import subprocess

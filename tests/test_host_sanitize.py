@@ -3,7 +3,7 @@ UndefinedBehaviorSanitizer, on the CPU.
 
 types.cpp and compile.cpp (constructors, layout compiler, segment queries)
 are compiled unchanged with the host compiler, with tests/native/host_stub.cpp
-in place of the device tables, and linked with the oracle; the driver
+in place of the device tables, and linked with the oracle; the test program
 (tests/native/host_sanitize.cpp) builds 2000 seeded random nested types on
 both sides, compares attributes, segments (one element and counts 0, 2, 3)
 and iov_len budgets, runs envelope/contents, layout info and the error paths,
