@@ -53,6 +53,18 @@ struct BatchReq {
 // Tile bodies a request needs its direction's kernel to carry.
 int body_bits(const ReqDesc &d) { return d.body | (d.body == BODY_RELAY ? d.pbody | d.ubody : 0); }
 
+// A pack direction whose requests all take the chunk body gathers through
+// the caches when some request's runs are shorter than a line: those lines
+// hold runs that other tiles (often of other requests) read soon after,
+// such as the width-1 and width-4 faces of one side of an array.  Longer
+// runs stream.
+constexpr int64_t CACHED_RUN_MAX = 127;
+
+int dir_body(int body, int dir, int64_t min_mean_run)
+{
+    return dir == 0 && body == BODY_CHUNK && min_mean_run <= CACHED_RUN_MAX ? (BODY_CHUNK | BODY_CACHED) : body;
+}
+
 // Chunks per tile of a request.  In typed-address order a request of short
 // runs gets proportionally shorter tiles (down to a quarter), so that tiles
 // of requests whose runs share cache lines -- the width-1 and width-4 faces
@@ -283,12 +295,14 @@ int stage(mdt_batch_s *b, hipStream_t s)
     // pack requests first, then unpack, each in the order they were added
     for (int dir = 0; dir < 2; dir++) {
         const int64_t acc0 = acc;
+        int64_t min_run = INT64_MAX;
         for (size_t i = 0; i < b->reqs.size(); i++) {
             if (b->reqs[i].d.unpack != dir) continue;
             D[k] = b->reqs[i].d;
             D[k].tc = tile_chunks_of(b->cfg, b->reqs[i]);
             b->lds_dir[dir] = std::max(b->lds_dir[dir], b->reqs[i].lds);
             b->body_dir[dir] |= body_bits(D[k]);
+            min_run = std::min(min_run, b->reqs[i].mean_run);
             tile0[k] = acc;
             acc += (D[k].nchunks + D[k].tc - 1) / D[k].tc;
             H.nreq_dir[dir]++;
@@ -296,6 +310,7 @@ int stage(mdt_batch_s *b, hipStream_t s)
         }
         H.ntiles_dir[dir] = acc - acc0;
         b->ntiles_dir[dir] = acc - acc0;
+        b->body_dir[dir] = dir_body(b->body_dir[dir], dir, min_run);
         if (acc > acc0) b->dirs |= 1 << dir;
     }
     tile0[k] = acc;
@@ -611,6 +626,7 @@ int launch_noalloc(mdt_batch_s *b, hipStream_t s)
     BatchHeader H{};
     H.tile_chunks = T;
     int32_t lds_dir[2] = {0, 0}, body_dir[2] = {0, 0};
+    int64_t min_run[2] = {INT64_MAX, INT64_MAX};
     int64_t packed = 0;
     for (const BatchReq &r : b->reqs) {
         const int dir = r.d.unpack;
@@ -618,8 +634,10 @@ int launch_noalloc(mdt_batch_s *b, hipStream_t s)
         H.ntiles_dir[dir] += (r.d.nchunks + T - 1) / T;  // request order: every request at T
         lds_dir[dir] = std::max(lds_dir[dir], r.lds);
         body_dir[dir] |= body_bits(r.d);
+        min_run[dir] = std::min(min_run[dir], r.mean_run);
         if (!dir && !r.type2) packed += r.d.nbytes;
     }
+    for (int dir = 0; dir < 2; dir++) body_dir[dir] = dir_body(body_dir[dir], dir, min_run[dir]);
     H.keep_packed = packed <= KEEP_PACKED_MAX ? 1 : 0;
     if (H.ntiles_dir[0] + H.ntiles_dir[1] > INT32_MAX) return MDT_ERR_COUNT;
     // stage the descriptors, pack requests first, in chunks

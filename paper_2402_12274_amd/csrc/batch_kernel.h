@@ -34,6 +34,7 @@ constexpr int BODY_CHUNK = 4;  // chunk path
 constexpr int BODY_ALL = 7;
 constexpr int BODY_COPY = 8;   // typed copy (runs with the pack direction)
 constexpr int BODY_RELAY = 16; // pack, then unpack of the same packed bytes (runs with the pack direction)
+constexpr int BODY_CACHED = 32; // with BODY_CHUNK alone, pack: gathers load through the caches
 
 // Descriptors are stored pack requests first, so each direction's tiles
 // form one range: [0, ntiles_dir[0]) for pack, then unpack.
@@ -122,9 +123,10 @@ __device__ __forceinline__ void run_tile(const DevLayout &L, const XferArgs &A, 
                 else if (kind == KIND_SINGLE) unpack_tile4<KIND_SINGLE>(L, A, s0, s1);
                 else unpack_tile4<KIND_MULTI>(L, A, s0, s1);
             } else {
-                if (kind == KIND_CONTIG) pack_tile4<KIND_CONTIG>(L, A, s0, s1);
-                else if (kind == KIND_SINGLE) pack_tile4<KIND_SINGLE>(L, A, s0, s1);
-                else pack_tile4<KIND_MULTI>(L, A, s0, s1);
+                constexpr bool CACHED = (BODY & BODY_CACHED) != 0;
+                if (kind == KIND_CONTIG) pack_tile4<KIND_CONTIG, CACHED>(L, A, s0, s1);
+                else if (kind == KIND_SINGLE) pack_tile4<KIND_SINGLE, CACHED>(L, A, s0, s1);
+                else pack_tile4<KIND_MULTI, CACHED>(L, A, s0, s1);
             }
         }
     }
@@ -253,6 +255,7 @@ void launch_batch_dir_impl(dim3 grid, size_t lds, hipStream_t s, const BatchHead
     else if (!UNPACK && (body & BODY_COPY)) MDT_LAUNCH(UNPACK ? BODY_ALL : (BODY_ALL | BODY_COPY));
     else if (body == BODY_DENSE) MDT_LAUNCH(BODY_DENSE);
     else if (body == BODY_RUNS) MDT_LAUNCH(BODY_RUNS);
+    else if (!UNPACK && body == (BODY_CHUNK | BODY_CACHED)) MDT_LAUNCH(UNPACK ? BODY_ALL : (BODY_CHUNK | BODY_CACHED));
     else if (body == BODY_CHUNK) MDT_LAUNCH(BODY_CHUNK);
     else MDT_LAUNCH(BODY_ALL);
 #undef MDT_LAUNCH

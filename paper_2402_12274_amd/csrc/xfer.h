@@ -72,13 +72,15 @@ __device__ __forceinline__ uint32_t byte_at(const V4 &a, int pos)
 __device__ __forceinline__ uint32_t dword_at(const V4 &a, int pos) { return (uint32_t)(as128(a) >> (8 * pos)); }
 
 // 16 bytes from an arbitrarily aligned source; every dword loaded holds at
-// least one of the 16 bytes, so no access leaves the source's pages.
+// least one of the 16 bytes, so no access leaves the source's pages.  An
+// aligned load streams past the caches unless CACHED.
+template <bool CACHED = false>
 __device__ __forceinline__ V4 load16(const uint8_t *s)
 {
     uintptr_t u = (uintptr_t)s;
     V4 r;
     if ((u & 15) == 0) {
-        u32x4 v = __builtin_nontemporal_load(gptr((const u32x4 *)s));
+        u32x4 v = CACHED ? *gptr((const u32x4 *)s) : __builtin_nontemporal_load(gptr((const u32x4 *)s));
         r.w0 = v.x; r.w1 = v.y; r.w2 = v.z; r.w3 = v.w;
     } else if ((u & 7) == 0) {
         const MDT_G u32x2 *p = gptr((const u32x2 *)s);
@@ -198,7 +200,7 @@ __device__ __forceinline__ void scatter(const V4 &acc, int k, uint8_t *d, int n)
 // ---------------------------------------------------------------------------
 // chunk bodies
 
-template <int KIND>
+template <int KIND, bool CACHED>
 __device__ __forceinline__ void pack_chunk(const DevLayout &L, const XferArgs &A, int64_t c)
 {
     int64_t lo = 16 * c - A.head;
@@ -211,7 +213,7 @@ __device__ __forceinline__ void pack_chunk(const DevLayout &L, const XferArgs &A
     const uint8_t *src = A.typed;
     Loc l = locate<KIND>(L, p, A.elem1);
     if (n == 16 && l.rem >= 16) {
-        acc = load16(src + l.addr);
+        acc = load16<CACHED>(src + l.addr);
     } else {
         // the first two runs are located before either is read, so their
         // loads are in flight together (chunks of small blocks mostly hold
@@ -281,14 +283,14 @@ __device__ __forceinline__ void unpack_chunk(const DevLayout &L, const XferArgs 
 
 // Load chunk c whole when its bytes lie in one run or in two dword-aligned
 // runs; false when it needs the general body (or lies outside the tile).
-template <int KIND>
+template <int KIND, bool CACHED>
 __device__ __forceinline__ bool pack_first(const DevLayout &L, const XferArgs &A, int64_t c, int64_t cend, V4 &acc)
 {
     int64_t lo = 16 * c - A.head;
     if (c < cend && lo >= 0 && lo + 16 <= A.nbytes) {
         Loc l = locate<KIND>(L, (uint64_t)(A.off + lo), A.elem1);
         if (l.rem >= 16) {
-            acc = load16(A.typed + l.addr);
+            acc = load16<CACHED>(A.typed + l.addr);
             return true;
         }
         // two runs split on a dword boundary, both dword aligned (blocks of
@@ -407,8 +409,10 @@ __device__ __forceinline__ void unpack_tile_run(const XferArgs &A, int64_t c0, i
 // chunk whose 16 bytes lie in one run, or in two dword-aligned runs, is
 // loaded before any store is issued, so up to four gathers per lane are in
 // flight at once.  The other chunks then take the general body, one at a
-// time.  A tile that lies inside one run is a plain copy.
-template <int KIND>
+// time.  A tile that lies inside one run is a plain copy.  CACHED: the
+// gathers load through the caches (a launch over runs shorter than a line,
+// whose lines other runs read soon after), else they stream.
+template <int KIND, bool CACHED = false>
 __device__ __forceinline__ void pack_tile4(const DevLayout &L, const XferArgs &A, int64_t c0, int64_t cend)
 {
     if (KIND != KIND_CONTIG) {
@@ -420,9 +424,10 @@ __device__ __forceinline__ void pack_tile4(const DevLayout &L, const XferArgs &A
     }
     const int64_t c = c0 + threadIdx.x;
     V4 a0 = {0u, 0u, 0u, 0u}, a1 = a0, a2 = a0, a3 = a0;
-    uint32_t fast = (uint32_t)pack_first<KIND>(L, A, c, cend, a0) | (uint32_t)pack_first<KIND>(L, A, c + 256, cend, a1) << 1 |
-                    (uint32_t)pack_first<KIND>(L, A, c + 512, cend, a2) << 2 |
-                    (uint32_t)pack_first<KIND>(L, A, c + 768, cend, a3) << 3;
+    uint32_t fast = (uint32_t)pack_first<KIND, CACHED>(L, A, c, cend, a0) |
+                    (uint32_t)pack_first<KIND, CACHED>(L, A, c + 256, cend, a1) << 1 |
+                    (uint32_t)pack_first<KIND, CACHED>(L, A, c + 512, cend, a2) << 2 |
+                    (uint32_t)pack_first<KIND, CACHED>(L, A, c + 768, cend, a3) << 3;
     if (fast & 1u) store_chunk(A, c, a0);
     if (fast & 2u) store_chunk(A, c + 256, a1);
     if (fast & 4u) store_chunk(A, c + 512, a2);
@@ -430,7 +435,7 @@ __device__ __forceinline__ void pack_tile4(const DevLayout &L, const XferArgs &A
 #pragma unroll 1
     for (int k = 0; k < 4; k++) {
         int64_t ck = c + 256 * k;
-        if (ck < cend && !((fast >> k) & 1u)) pack_chunk<KIND>(L, A, ck);
+        if (ck < cend && !((fast >> k) & 1u)) pack_chunk<KIND, CACHED>(L, A, ck);
     }
 }
 
